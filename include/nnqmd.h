@@ -1,0 +1,150 @@
+/*
+ * nnqmd.h - C ABI of the MI355X (gfx950) energy/force library for an
+ * Allegro-style neural-network interatomic potential.
+ *
+ * The library evaluates, for a periodic orthorhombic box of atoms, the total
+ * potential energy E built from pairwise embedding energies E_ij of atom pairs
+ * within a cutoff, and the forces f_i = -dE/dr_i, and advances Newton's
+ * equations m_i d^2 r_i/dt^2 = f_i (paper Sec. 2.1, Eq. 1). Pairs are found
+ * with a linked-cell neighbour list (Sec. 2.4). The equivariant edge model
+ * (radial Bessel basis with polynomial cutoff, real spherical harmonics Y_l,
+ * two-body / latent / edge MLPs, environment sums over neighbours,
+ * Clebsch-Gordan tensor products; Sec. 2.1) is written out in the library's
+ * design notes; forces come from a hand-written adjoint of every step.
+ *
+ * Conventions shared by every entry point
+ *   - Units: Angstrom, eV, fs, amu. Forces in eV/A.
+ *   - Arrays are contiguous, row-major. Unless stated otherwise an array
+ *     pointer is a DEVICE pointer (e.g. torch.Tensor.data_ptr() of a CUDA/HIP
+ *     tensor) on the context's device, owned by the caller, and must stay valid
+ *     until the work queued on the context's stream has finished.
+ *   - cell[3] is a HOST array with the three orthorhombic box lengths.
+ *   - All GPU work is queued asynchronously on the context's stream; results
+ *     are valid after that stream is synchronised. Calls on one context must
+ *     not overlap (a context is not thread-safe).
+ *   - Errors are returned as nq_status; no C++ exception crosses the ABI. The
+ *     message of the last error on a context is available from nq_last_error.
+ *   - Model weights are one flat FP64 host blob; each segment is a row-major
+ *     [fan_in, fan_out] matrix of a linear map y = x W (no biases), in the order
+ *     reported by nq_model_weight_layout.
+ */
+#ifndef NNQMD_H
+#define NNQMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  NQ_OK = 0,
+  NQ_ERR_ARG = -1,          /* bad pointer, size, species or geometry argument */
+  NQ_ERR_UNSUPPORTED = -2,  /* model shape or option this build does not support */
+  NQ_ERR_CAPACITY = -3,     /* neighbour-list row or edge capacity exceeded */
+  NQ_ERR_NUMERIC = -4,      /* non-finite value or coincident atoms detected */
+  NQ_ERR_DEVICE = -5,       /* HIP runtime error */
+  NQ_ERR_OOM = -6           /* device allocation failed */
+} nq_status;
+
+enum { NQ_PRECISION_FP32 = 0, NQ_PRECISION_BF16 = 1 };
+
+typedef struct nq_ctx nq_ctx;
+typedef struct nq_model nq_model;
+
+/* Model hyper-parameters. Widths of MLP layers are listed without the input
+ * width; twobody[n_twobody-1] is the latent width D and latent[n_latent-1] must
+ * equal D. lmax <= 2. n_species <= 8. precision selects the arithmetic of the
+ * per-edge MLP products: NQ_PRECISION_FP32 (FP32 everywhere) or
+ * NQ_PRECISION_BF16 (BF16 operands on the matrix cores with FP32 accumulation;
+ * tensor products, reductions and everything else stay FP32/FP64). */
+typedef struct {
+  int32_t n_species, n_bessel, poly_p, lmax, n_layers, channels;
+  int32_t n_twobody, twobody[4];
+  int32_t n_latent, latent[4];
+  int32_t n_edge, edge[4];
+  double r_cut;             /* cutoff r_c in A */
+  double avg_num_neighbors; /* nu: environment sums are scaled by nu^-1/2 */
+  double energy_scale;      /* sigma_E multiplying every E_ij */
+  int32_t precision;
+} nq_model_desc;
+
+/* Create a context on HIP device `device` that queues work on `hip_stream`
+ * (a hipStream_t; NULL = the null stream). */
+nq_status nq_ctx_create(int device, void* hip_stream, nq_ctx** out);
+/* Change the stream of an existing context. */
+nq_status nq_ctx_set_stream(nq_ctx* ctx, void* hip_stream);
+void nq_ctx_destroy(nq_ctx* ctx);
+
+/* Host-only: the weight segments a model with this description expects.
+ * shapes[2*s] = fan_in, shapes[2*s+1] = fan_out of segment s, for s <
+ * min(*n_segments, max_segments). shapes may be NULL to query the count.
+ * *n_weights receives the total number of FP64 values. */
+nq_status nq_model_weight_layout(const nq_model_desc* desc, int64_t* shapes, int32_t max_segments,
+                                 int32_t* n_segments, int64_t* n_weights);
+
+/* Copy a model to the context's device. `weights` is a HOST array of n_weights
+ * FP64 values (see nq_model_weight_layout); it is not retained. The model
+ * derives its FP32 and BF16 copies (round to nearest even) and its coupling
+ * tables itself. */
+nq_status nq_model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* weights,
+                          int64_t n_weights, nq_model** out);
+void nq_model_destroy(nq_model* model);
+
+/* Build the linked-cell neighbour list (Sec. 2.4) of n atoms at positions
+ * pos[n*3] (device, FP64) for the list radius r_cut + skin. Rows are sorted by
+ * neighbour index. Requires r_cut + skin < min(cell)/2 (minimum image).
+ * Returns NQ_ERR_CAPACITY if a row still overflows after the row capacity was
+ * grown once. Synchronises the stream once to size the edge workspace. */
+nq_status nq_neighbor_build(nq_ctx* ctx, const double* pos, int64_t n, const double cell[3],
+                            double r_cut, double skin);
+
+/* Energy and forces (Sec. 2.1, Eq. 1) of the current positions pos[n*3]
+ * (device, FP64) with species[n] (device, int32 in [0, n_species)).
+ * energy[1] (device, FP64) receives E; forces[n*3] (device, FP64) receives
+ * -dE/dr; atom_energy[n] (device, FP64, or NULL) receives E_i = sum_j E_ij.
+ * Uses the context's neighbour list; builds it (skin 1.0 A) if there is none
+ * for this n/cell, or if an atom moved more than half the skin since the last
+ * build. Returns NQ_ERR_ARG if n or cell differ from the list's and no rebuild
+ * is possible. Asynchronous: nothing is synchronised. */
+nq_status nq_energy_forces(nq_ctx* ctx, const nq_model* model, const double* pos,
+                           const int32_t* species, int64_t n, const double cell[3], double* energy,
+                           double* forces, double* atom_energy);
+
+/* n_steps velocity-Verlet steps (Eq. 1) of length dt_fs: v += dt/2 F/m;
+ * r += dt v (wrapped into the box); F = F(r); v += dt/2 F/m. pos[n*3], vel[n*3]
+ * (device, FP64, A and A/fs) are updated in place; inv_mass[n] (device, FP64,
+ * 1/amu). forces[n*3] (device, FP64) must hold F(pos) on entry (e.g. from
+ * nq_energy_forces) and holds F of the final positions on return. epot/ekin
+ * (device, FP64, [n_steps] each, or NULL) receive the potential and kinetic
+ * energy after every step. The neighbour list is rebuilt on the device
+ * whenever an atom has moved more than half the skin since the last build.
+ * One step is captured once as a HIP graph and replayed. */
+nq_status nq_step(nq_ctx* ctx, const nq_model* model, double* pos, double* vel,
+                  const double* inv_mass, const int32_t* species, int64_t n, const double cell[3],
+                  double dt_fs, int32_t n_steps, double* forces, double* epot, double* ekin);
+
+/* Number of in-cutoff directed edges of the last nq_energy_forces / nq_step
+ * evaluation, and of neighbour-list rebuilds so far. Synchronises the stream. */
+nq_status nq_stats(nq_ctx* ctx, int64_t* n_edges, int64_t* n_rebuilds);
+
+/* Copy the directed in-cutoff edges (i, j) of the last evaluation, sorted by
+ * (i, j), into ei[cap], ej[cap] (device, int32). *n_edges (host) receives the
+ * count; returns NQ_ERR_CAPACITY if it exceeds cap. Synchronises the stream. */
+nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, int64_t* n_edges);
+
+/* Copy a named per-edge or per-atom intermediate of the last evaluation into
+ * out[cap] (device, FP32) and report its row count and width (host). Names:
+ * "geom" (d, u, Y...), "x0", "w0", "gamma<t>", "s<t>", "x<t>", "V<t>", "eij",
+ * "g" (dE/dr_ij). For parity tests of single stages. Synchronises the stream. */
+nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
+                          int64_t cap, int64_t* rows, int64_t* width);
+
+const char* nq_status_str(nq_status status);
+const char* nq_last_error(const nq_ctx* ctx);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* NNQMD_H */

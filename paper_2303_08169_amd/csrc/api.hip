@@ -1,0 +1,394 @@
+// C ABI of the library (declared in include/nnqmd.h). Every entry point turns
+// internal errors into an nq_status and records the message on the context.
+#include <cmath>
+#include <cstring>
+#include <exception>
+
+#include "nq_internal.hpp"
+
+namespace nq {
+void md_record_async(hipStream_t s, const double* epot_now, const double* ekin_now, int* counter, double* epot,
+                     double* ekin, int n_steps);
+void md_set_int_async(hipStream_t s, int* p, int v);
+}  // namespace nq
+
+using namespace nq;
+
+namespace {
+
+thread_local std::string g_error;
+
+template <class F>
+nq_status guarded(nq_ctx* ctx, F&& f) {
+  try {
+    f();
+    return NQ_OK;
+  } catch (const Error& e) {
+    (ctx ? ctx->last_error : g_error) = e.msg;
+    return e.status;
+  } catch (const std::bad_alloc&) {
+    (ctx ? ctx->last_error : g_error) = "host allocation failed";
+    return NQ_ERR_OOM;
+  } catch (const std::exception& e) {
+    (ctx ? ctx->last_error : g_error) = e.what();
+    return NQ_ERR_DEVICE;
+  }
+}
+
+void read_flags(nq_ctx* ctx, int* host) {
+  NQ_HIP(hipMemcpyAsync(host, ctx->nl.flags.p, 8 * sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+  NQ_HIP(hipStreamSynchronize(ctx->stream));
+}
+
+void zero_flags(nq_ctx* ctx) { NQ_HIP(hipMemsetAsync(ctx->nl.flags.p, 0, 8 * sizeof(int), ctx->stream)); }
+
+void check_flags(nq_ctx* ctx) {
+  int f[8];
+  read_flags(ctx, f);
+  if (f[2]) {
+    zero_flags(ctx);
+    throw Error{NQ_ERR_NUMERIC, "non-finite coordinate or two atoms closer than 0.1 A"};
+  }
+  if (f[0] > 0) {
+    zero_flags(ctx);
+    throw Error{NQ_ERR_CAPACITY, "a neighbour-list row overflowed (" + std::to_string(f[0]) + " > " +
+                                     std::to_string(ctx->nl.k_max) + ")"};
+  }
+  if (f[5]) {
+    zero_flags(ctx);
+    throw Error{NQ_ERR_ARG, "species outside [0, n_species)"};
+  }
+  if (f[4] > 0) {
+    zero_flags(ctx);
+    throw Error{NQ_ERR_CAPACITY, "edge workspace overflowed (" + std::to_string(f[4]) + " edges)"};
+  }
+}
+
+void neighbor_build_sync(nq_ctx* ctx, const double* pos, int64_t n, const double cell[3], double r_cut,
+                         double skin) {
+  NQ_HIP(hipSetDevice(ctx->device));
+  nbr_configure(ctx, n, cell, r_cut, skin);
+  NbrList& nl = ctx->nl;
+  for (int attempt = 0;; ++attempt) {
+    zero_flags(ctx);
+    nbr_build_async(ctx, pos, false);
+    int f[8];
+    read_flags(ctx, f);
+    if (f[2]) {
+      zero_flags(ctx);
+      throw Error{NQ_ERR_NUMERIC, "non-finite coordinate"};
+    }
+    if (f[0] == 0) break;
+    NQ_REQUIRE(attempt == 0, NQ_ERR_CAPACITY,
+               "neighbour-list row overflow after growing the row capacity to " + std::to_string(nl.k_max));
+    nl.k_max = (int)std::max<int64_t>(rup((int64_t)(1.5 * nl.k_max), 32), rup(f[0] + 16, 32));
+    NQ_REQUIRE(nl.k_max <= 2048, NQ_ERR_CAPACITY, "neighbour rows longer than 2048");
+    nl.nbr.release();
+    nl.nbr.ensure((size_t)n * nl.k_max * 4);
+  }
+  std::vector<int> cnt(n);
+  NQ_HIP(hipMemcpy(cnt.data(), nl.nbr_cnt.p, n * sizeof(int), hipMemcpyDeviceToHost));
+  int64_t tot = 0;
+  for (int c : cnt) tot += c;
+  nl.n_entries = tot;
+  nl.built = true;
+  zero_flags(ctx);
+}
+
+double default_skin(const double cell[3], double rc) {
+  const double lmin = std::min(cell[0], std::min(cell[1], cell[2]));
+  const double room = 0.5 * lmin - rc;
+  NQ_REQUIRE(room > 0, NQ_ERR_ARG, "the cutoff must be below half of every box length (minimum image)");
+  return std::min(1.0, 0.9 * room);
+}
+
+// Make sure a neighbour list valid for this model exists and the workspace fits it.
+void ensure_list(nq_ctx* ctx, const nq_model* m, const double* pos, int64_t n, const double cell[3]) {
+  NbrList& nl = ctx->nl;
+  const double rc = m->dims.rc;
+  const bool ok = nl.built && nl.n == n && nl.box[0] == cell[0] && nl.box[1] == cell[1] && nl.box[2] == cell[2] &&
+                  nl.r_cut + nl.skin >= rc;
+  if (!ok) neighbor_build_sync(ctx, pos, n, cell, rc, default_skin(cell, rc));
+  const int64_t cap = rup((int64_t)(1.25 * (double)nl.n_entries) + 1024, 128);
+  ws_ensure(ctx, m, cap, n);
+}
+
+void check_common(nq_ctx* ctx, const nq_model* m, const double* pos, const int32_t* species, int64_t n,
+                  const double* cell) {
+  NQ_REQUIRE(ctx && m && pos && species && cell, NQ_ERR_ARG, "null argument");
+  NQ_REQUIRE(m->ctx == ctx, NQ_ERR_ARG, "model belongs to another context");
+  NQ_REQUIRE(n >= 2 && n < ((int64_t)1 << 30), NQ_ERR_ARG, "n out of range");
+  for (int k = 0; k < 3; ++k) NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0, NQ_ERR_ARG, "bad cell");
+}
+
+void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int32_t* species, int64_t n,
+                    double* energy, double* forces, double* atom_energy) {
+  NbrList& nl = ctx->nl;
+  const double half = 0.5 * (nl.r_cut + nl.skin - m->dims.rc);
+  nbr_displacement_check_async(ctx, pos, half);
+  nbr_build_async(ctx, pos, true);
+  edges_build_async(ctx, pos, m->dims.rc);
+  forward_async(ctx, m, species, n, energy, atom_energy);
+  backward_async(ctx, m, n, forces);
+}
+
+}  // namespace
+
+extern "C" {
+
+nq_status nq_ctx_create(int device, void* hip_stream, nq_ctx** out) {
+  return guarded(nullptr, [&] {
+    NQ_REQUIRE(out, NQ_ERR_ARG, "null out");
+    int count = 0;
+    NQ_HIP(hipGetDeviceCount(&count));
+    NQ_REQUIRE(device >= 0 && device < count, NQ_ERR_ARG, "no such device");
+    NQ_HIP(hipSetDevice(device));
+    nq_ctx* c = new nq_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    *out = c;
+  });
+}
+
+nq_status nq_ctx_set_stream(nq_ctx* ctx, void* hip_stream) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx, NQ_ERR_ARG, "null ctx");
+    ctx->stream = (hipStream_t)hip_stream;
+  });
+}
+
+void nq_ctx_destroy(nq_ctx* ctx) {
+  if (!ctx) return;
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  if (ctx->graph_exec) (void)hipGraphExecDestroy(ctx->graph_exec);
+  if (ctx->md_stream) (void)hipStreamDestroy(ctx->md_stream);
+  if (ctx->ev[0]) (void)hipEventDestroy(ctx->ev[0]);
+  if (ctx->ev[1]) (void)hipEventDestroy(ctx->ev[1]);
+  delete ctx;
+}
+
+nq_status nq_model_weight_layout(const nq_model_desc* desc, int64_t* shapes, int32_t max_segments,
+                                 int32_t* n_segments, int64_t* n_weights) {
+  return guarded(nullptr, [&] {
+    NQ_REQUIRE(desc && n_segments && n_weights, NQ_ERR_ARG, "null argument");
+    std::vector<std::pair<int64_t, int64_t>> segs;
+    weight_layout(*desc, segs);
+    *n_segments = (int32_t)segs.size();
+    int64_t tot = 0;
+    for (size_t s = 0; s < segs.size(); ++s) {
+      if (shapes && (int32_t)s < max_segments) {
+        shapes[2 * s] = segs[s].first;
+        shapes[2 * s + 1] = segs[s].second;
+      }
+      tot += segs[s].first * segs[s].second;
+    }
+    *n_weights = tot;
+  });
+}
+
+nq_status nq_model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* weights, int64_t n_weights,
+                          nq_model** out) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && desc && weights && out, NQ_ERR_ARG, "null argument");
+    *out = model_create(ctx, desc, weights, n_weights);
+  });
+}
+
+void nq_model_destroy(nq_model* model) {
+  if (!model) return;
+  nq_ctx* ctx = model->ctx;
+  if (ctx) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    if (ctx->ws.model == model) {
+      ctx->ws.model = nullptr;
+      ctx->ws.cap = 0;
+      ctx->ws.bufs.clear();
+    }
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+      ctx->graph_key.clear();
+    }
+  }
+  delete model;
+}
+
+nq_status nq_neighbor_build(nq_ctx* ctx, const double* pos, int64_t n, const double cell[3], double r_cut,
+                            double skin) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && pos && cell, NQ_ERR_ARG, "null argument");
+    NQ_REQUIRE(std::isfinite(r_cut) && std::isfinite(skin), NQ_ERR_ARG, "bad r_cut or skin");
+    neighbor_build_sync(ctx, pos, n, cell, r_cut, skin);
+  });
+}
+
+nq_status nq_energy_forces(nq_ctx* ctx, const nq_model* model, const double* pos, const int32_t* species,
+                           int64_t n, const double cell[3], double* energy, double* forces, double* atom_energy) {
+  return guarded(ctx, [&] {
+    check_common(ctx, model, pos, species, n, cell);
+    NQ_REQUIRE(energy && forces, NQ_ERR_ARG, "null output");
+    NQ_HIP(hipSetDevice(ctx->device));
+    ensure_list(ctx, model, pos, n, cell);
+    evaluate_async(ctx, model, pos, species, n, energy, forces, atom_energy);
+  });
+}
+
+nq_status nq_step(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const double* inv_mass,
+                  const int32_t* species, int64_t n, const double cell[3], double dt_fs, int32_t n_steps,
+                  double* forces, double* epot, double* ekin) {
+  return guarded(ctx, [&] {
+    check_common(ctx, model, pos, species, n, cell);
+    NQ_REQUIRE(vel && inv_mass && forces, NQ_ERR_ARG, "null argument");
+    NQ_REQUIRE(n_steps >= 0 && std::isfinite(dt_fs) && dt_fs > 0, NQ_ERR_ARG, "bad dt or n_steps");
+    if (n_steps == 0) return;
+    NQ_HIP(hipSetDevice(ctx->device));
+    ensure_list(ctx, model, pos, n, cell);
+    if (!ctx->md_stream) {
+      NQ_HIP(hipStreamCreateWithFlags(&ctx->md_stream, hipStreamNonBlocking));
+      NQ_HIP(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
+      NQ_HIP(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
+    }
+    ctx->md_scratch.ensure(64);
+    double* ek_now = ctx->md_scratch.as<double>();
+    int* counter = reinterpret_cast<int*>(ctx->md_scratch.as<double>() + 2);
+    std::vector<const void*> key = {model,  pos,  vel,  inv_mass, species, forces,
+                                    epot,   ekin, (const void*)(intptr_t)n,
+                                    (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
+                                    ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p};
+    double dtkey;
+    std::memcpy(&dtkey, &dt_fs, sizeof(double));
+    key.push_back((const void*)(intptr_t)(*(int64_t*)&dtkey));
+    for (int k = 0; k < 3; ++k) {
+      int64_t b;
+      std::memcpy(&b, &cell[k], 8);
+      key.push_back((const void*)(intptr_t)b);
+    }
+    hipStream_t user = ctx->stream;
+    if (!ctx->graph_exec || key != ctx->graph_key) {
+      if (ctx->graph_exec) {
+        (void)hipGraphExecDestroy(ctx->graph_exec);
+        ctx->graph_exec = nullptr;
+      }
+      ctx->stream = ctx->md_stream;
+      hipGraph_t graph = nullptr;
+      try {
+        NQ_HIP(hipStreamBeginCapture(ctx->md_stream, hipStreamCaptureModeThreadLocal));
+        md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
+        md_drift_async(ctx->md_stream, pos, vel, n, dt_fs, cell);
+        evaluate_async(ctx, model, pos, species, n, ctx->ws.esum, forces, nullptr);
+        md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
+        md_ekin_async(ctx->md_stream, vel, inv_mass, n, ek_now);
+        md_record_async(ctx->md_stream, ctx->ws.esum, ek_now, counter, epot, ekin, n_steps);
+        NQ_HIP(hipStreamEndCapture(ctx->md_stream, &graph));
+        NQ_HIP(hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0));
+        (void)hipGraphDestroy(graph);
+      } catch (...) {
+        hipGraph_t dummy = nullptr;
+        (void)hipStreamEndCapture(ctx->md_stream, &dummy);
+        if (dummy) (void)hipGraphDestroy(dummy);
+        if (graph) (void)hipGraphDestroy(graph);
+        ctx->stream = user;
+        throw;
+      }
+      ctx->stream = user;
+      ctx->graph_key = key;
+    }
+    NQ_HIP(hipEventRecord(ctx->ev[0], user));
+    NQ_HIP(hipStreamWaitEvent(ctx->md_stream, ctx->ev[0], 0));
+    md_set_int_async(ctx->md_stream, counter, 0);
+    for (int s = 0; s < n_steps; ++s) NQ_HIP(hipGraphLaunch(ctx->graph_exec, ctx->md_stream));
+    NQ_HIP(hipEventRecord(ctx->ev[1], ctx->md_stream));
+    NQ_HIP(hipStreamWaitEvent(user, ctx->ev[1], 0));
+    NQ_HIP(hipStreamSynchronize(ctx->md_stream));
+    check_flags(ctx);
+  });
+}
+
+nq_status nq_stats(nq_ctx* ctx, int64_t* n_edges, int64_t* n_rebuilds) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx, NQ_ERR_ARG, "null ctx");
+    int ne = 0;
+    if (ctx->ws.nedge.p) {
+      NQ_HIP(hipMemcpyAsync(&ne, ctx->ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    }
+    int f[8] = {0};
+    if (ctx->nl.flags.p) read_flags(ctx, f);
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    if (n_edges) *n_edges = ne;
+    if (n_rebuilds) *n_rebuilds = f[3];
+    if (ctx->nl.flags.p) check_flags(ctx);
+  });
+}
+
+nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, int64_t* n_edges) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && ei && ej && n_edges, NQ_ERR_ARG, "null argument");
+    NQ_REQUIRE(ctx->ws.nedge.p, NQ_ERR_ARG, "no evaluation yet");
+    int ne = 0;
+    NQ_HIP(hipMemcpyAsync(&ne, ctx->ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    *n_edges = ne;
+    NQ_REQUIRE(ne <= cap, NQ_ERR_CAPACITY, "output too small");
+    NQ_HIP(hipMemcpyAsync(ei, ctx->ws.ei.p, (size_t)ne * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    NQ_HIP(hipMemcpyAsync(ej, ctx->ws.ej.p, (size_t)ne * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out, int64_t cap,
+                          int64_t* rows, int64_t* width) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && model && name && out && rows && width, NQ_ERR_ARG, "null argument");
+    const Workspace& ws = ctx->ws;
+    NQ_REQUIRE(ws.model == model && ws.nedge.p, NQ_ERR_ARG, "no evaluation of this model yet");
+    const Dims& d = model->dims;
+    int ne = 0;
+    NQ_HIP(hipMemcpyAsync(&ne, ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    const std::string s(name);
+    const float* src = nullptr;
+    int64_t r = ne, w = 0;
+    auto layer = [&](const char* pre) -> int {
+      const size_t k = std::strlen(pre);
+      if (s.compare(0, k, pre) != 0 || s.size() == k) return -1;
+      return std::atoi(s.c_str() + k);
+    };
+    int t;
+    if (s == "geom") { src = ws.geo; w = 16; }
+    else if (s == "h0") { src = ws.h0; w = ws.K0p; }
+    else if (s == "we1") { src = ws.we1; w = 2 * d.NW; }
+    else if (s == "eij") { src = ws.eij; w = 1; }
+    else if (s == "g") { src = reinterpret_cast<const float*>(ws.gr); w = 4; }
+    else if (s == "gu") { src = ws.gu; w = 1; }
+    else if (s == "gY") { src = ws.gY; w = 16; }
+    else if ((t = layer("gamma")) >= 1 && t <= d.T) { src = ws.gam[t]; w = d.NY * d.C; r = ws.n_atoms; }
+    else if ((t = layer("s")) >= 1 && t <= d.T) { src = ws.s[t]; w = d.nscal * d.C; }
+    else if ((t = layer("V")) >= 1 && t < d.T) { src = ws.V[t]; w = d.NY * d.C; }
+    else if ((t = layer("x")) >= 0 && t <= d.T) { src = ws.x[t]; w = d.D; }
+    NQ_REQUIRE(src, NQ_ERR_ARG, "unknown buffer name " + s);
+    *rows = r;
+    *width = w;
+    NQ_REQUIRE(r * w <= cap, NQ_ERR_CAPACITY, "output too small");
+    NQ_HIP(hipMemcpyAsync(out, src, (size_t)r * w * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+const char* nq_status_str(nq_status status) {
+  switch (status) {
+    case NQ_OK: return "ok";
+    case NQ_ERR_ARG: return "invalid argument";
+    case NQ_ERR_UNSUPPORTED: return "unsupported";
+    case NQ_ERR_CAPACITY: return "capacity exceeded";
+    case NQ_ERR_NUMERIC: return "numeric error";
+    case NQ_ERR_DEVICE: return "device error";
+    case NQ_ERR_OOM: return "out of device memory";
+  }
+  return "unknown status";
+}
+
+const char* nq_last_error(const nq_ctx* ctx) { return ctx ? ctx->last_error.c_str() : g_error.c_str(); }
+
+}  // extern "C"

@@ -1,0 +1,94 @@
+// Velocity-Verlet integration of Newton's equations (paper Sec. 2.1, Eq. 1) in FP64.
+//   v += dt/2 * F/m;  r += dt * v (wrapped into the box);  F = F(r);  v += dt/2 * F/m
+// Units: A, fs, amu, eV; 1 eV/(amu A) = 9.648533212e-3 A/fs^2 (CODATA 2018).
+#include "nq_internal.hpp"
+
+namespace nq {
+
+namespace {
+
+constexpr double kAcc = 9.648533212e-3;          // A/fs^2 per eV/(amu A)
+constexpr double kEvPerAmuA2fs2 = 1.0 / kAcc;    // eV per amu A^2/fs^2
+
+__global__ void k_half_kick(double* __restrict__ vel, const double* __restrict__ F,
+                            const double* __restrict__ inv_mass, int64_t n, double half_dt) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  vel[k] += half_dt * kAcc * F[k] * inv_mass[k / 3];
+}
+
+__global__ void k_drift(double* __restrict__ pos, const double* __restrict__ vel, int64_t n, double dt,
+                        double Lx, double Ly, double Lz) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= 3 * n) return;
+  const int ax = (int)(k % 3);
+  const double L = ax == 0 ? Lx : (ax == 1 ? Ly : Lz);
+  double x = pos[k] + dt * vel[k];
+  x -= L * floor(x / L);
+  if (x >= L) x -= L;
+  pos[k] = x;
+}
+
+__global__ __launch_bounds__(1024) void k_ekin(const double* __restrict__ vel, const double* __restrict__ inv_mass,
+                                               int64_t n, double* __restrict__ out) {
+  __shared__ double hs[1024], hc[1024];
+  double s = 0.0, c = 0.0;
+  for (int64_t a = threadIdx.x; a < n; a += blockDim.x) {
+    const double vx = vel[3 * a], vy = vel[3 * a + 1], vz = vel[3 * a + 2];
+    const double x = 0.5 * (vx * vx + vy * vy + vz * vz) / inv_mass[a] * kEvPerAmuA2fs2;
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  hs[threadIdx.x] = s;
+  hc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double a = hs[threadIdx.x], b = hs[threadIdx.x + o];
+      const double t = a + b;
+      const double err = (fabs(a) >= fabs(b)) ? (a - t) + b : (b - t) + a;
+      hs[threadIdx.x] = t;
+      hc[threadIdx.x] += hc[threadIdx.x + o] + err;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = hs[0] + hc[0];
+}
+
+// Appends this step's energies at the device-side step counter and advances it.
+__global__ void k_record(const double* __restrict__ epot_now, const double* __restrict__ ekin_now,
+                         int* counter, double* epot, double* ekin, int n_steps) {
+  const int s = *counter;
+  if (s < n_steps) {
+    if (epot) epot[s] = epot_now[0];
+    if (ekin) ekin[s] = ekin_now[0];
+  }
+  *counter = s + 1;
+}
+
+__global__ void k_set_int(int* p, int v) { *p = v; }
+
+}  // namespace
+
+void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass, int64_t n,
+                        double half_dt) {
+  k_half_kick<<<(unsigned)cdiv(3 * n, 256), 256, 0, s>>>(vel, forces, inv_mass, n, half_dt);
+}
+
+void md_drift_async(hipStream_t s, double* pos, const double* vel, int64_t n, double dt, const double box[3]) {
+  k_drift<<<(unsigned)cdiv(3 * n, 256), 256, 0, s>>>(pos, vel, n, dt, box[0], box[1], box[2]);
+}
+
+void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n, double* out) {
+  k_ekin<<<1, 1024, 0, s>>>(vel, inv_mass, n, out);
+}
+
+void md_record_async(hipStream_t s, const double* epot_now, const double* ekin_now, int* counter, double* epot,
+                     double* ekin, int n_steps) {
+  k_record<<<1, 1, 0, s>>>(epot_now, ekin_now, counter, epot, ekin, n_steps);
+}
+
+void md_set_int_async(hipStream_t s, int* p, int v) { k_set_int<<<1, 1, 0, s>>>(p, v); }
+
+}  // namespace nq

@@ -1,0 +1,196 @@
+// Internal declarations of the gfx950 energy/force library (not part of the ABI).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <memory>
+#include <string>
+#include <vector>
+
+#include "../../include/nnqmd.h"
+
+namespace nq {
+
+typedef __bf16 bf16;
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float floatx4 __attribute__((ext_vector_type(4)));
+
+constexpr int kMaxL = 2;                     // highest irrep order supported
+constexpr int kMaxNY = (kMaxL + 1) * (kMaxL + 1);
+constexpr int kMaxPaths = 11;
+
+// Error carrying status + message, thrown only inside the library and turned
+// into an nq_status at the ABI boundary.
+struct Error {
+  nq_status status;
+  std::string msg;
+};
+
+#define NQ_HIP(call)                                                                     \
+  do {                                                                                   \
+    hipError_t e_ = (call);                                                              \
+    if (e_ != hipSuccess)                                                                \
+      throw ::nq::Error{e_ == hipErrorOutOfMemory ? NQ_ERR_OOM : NQ_ERR_DEVICE,          \
+                        std::string(#call) + ": " + hipGetErrorString(e_)};              \
+  } while (0)
+
+#define NQ_REQUIRE(cond, status, msg)                     \
+  do {                                                    \
+    if (!(cond)) throw ::nq::Error{(status), (msg)};      \
+  } while (0)
+
+// A device allocation that grows on demand and frees itself.
+struct DevBuf {
+  void* p = nullptr;
+  size_t bytes = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    bytes = 0;
+  }
+  void ensure(size_t nbytes) {
+    if (nbytes <= bytes) return;
+    release();
+    NQ_HIP(hipMalloc(&p, nbytes ? nbytes : 1));
+    bytes = nbytes;
+  }
+  template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+// Derived sizes of one model.
+struct Dims {
+  int S, nb, p, L, T, C, D;
+  int NY;      // (L+1)^2 spherical-harmonic components
+  int NW;      // (L+1)*C per-edge weights of one l-block
+  int nscal;   // number of coupling paths with l3 = 0
+  int n_paths; // all coupling paths
+  int n_in2b;  // 2S + nb two-body input width
+  int n_tb, tb[4], n_lat, lat[4], n_edge, edge[4];
+  double rc, inv_sqrt_nu, sigma_e;
+  int prec;
+  int paths[kMaxPaths][3];
+  int path_l3_count[kMaxL + 1];
+};
+
+// One linear map y = x W stored for the matrix-core kernels.
+//  fwd: B operand of y = x W, laid out [Np][Kp] with K contiguous (W^T), Kp = fin
+//       padded to 32, Np = fout padded to 16.
+//  bwd: B operand of gx = gy W^T, laid out [Np][Kp] = W with fin padded to 16 rows
+//       and fout padded to 32 columns.
+struct Lin {
+  int fin = 0, fout = 0;
+  int kp_f = 0, np_f = 0, kp_b = 0, np_b = 0;
+  DevBuf f32_fwd, f32_bwd, bf_fwd, bf_bwd;
+};
+
+// Dense real coupling tables C^(l1,l2,l3)[m1][m2][m3], indexed by path triple.
+struct CGTable {
+  float v[kMaxL + 1][kMaxL + 1][kMaxL + 1][2 * kMaxL + 1][2 * kMaxL + 1][2 * kMaxL + 1];
+};
+
+}  // namespace nq
+
+struct nq_model {
+  nq_ctx* ctx = nullptr;
+  nq_model_desc desc{};
+  nq::Dims dims{};
+  std::vector<nq::Lin*> tb;                 // two-body layers
+  nq::Lin v0e1;                             // [W_V0 | W_env^1]
+  std::vector<nq::Lin*> env;                // W_env^t for t >= 2 (index t-1; [0] unused)
+  std::vector<std::vector<nq::Lin*>> lat;   // latent layers per layer t (index t-1)
+  std::vector<nq::Lin*> edge;               // hidden edge-MLP layers
+  nq::DevBuf wout;                          // [edge_last] f32 final edge weights
+  nq::DevBuf mix;                           // per layer t<T: concatenated W_mix^t_l3, f32
+  std::vector<int64_t> mix_off;             // offset (floats) of layer t's mix block
+  nq::DevBuf cg;                            // CGTable on the device
+  ~nq_model();
+};
+
+namespace nq {
+
+struct NbrList {
+  int64_t n = 0;
+  double box[3] = {0, 0, 0};
+  double r_cut = 0, skin = 0;
+  int nc[3] = {0, 0, 0};
+  int k_max = 0;
+  int64_t n_entries = 0;  // total skin-list entries at the last host-visible build
+  bool built = false;
+  DevBuf cell_count, cell_start, cell_fill, cell_atoms, atom_cell;
+  DevBuf nbr, nbr_cnt, pos_ref;
+  // flags[0] row overflow (largest row), [1] rebuild requested, [2] numeric problem,
+  // [3] rebuild count, [4] edge overflow (edge total), [5] species out of range
+  DevBuf flags;
+};
+
+// Per-edge workspace of the layered pipeline, sized for `cap` edges.
+struct Workspace {
+  int64_t cap = 0;
+  int64_t n_atoms = 0;
+  const nq_model* model = nullptr;
+  DevBuf ecnt, eoff, ei, ej, rev, rij, nedge;  // edge list (model independent)
+  std::vector<std::unique_ptr<DevBuf>> bufs;   // model-dependent buffers
+  int K0p = 0, maxw = 0;
+  float *geo = nullptr, *h0 = nullptr, *we1 = nullptr, *eij = nullptr;
+  float *gx = nullptr, *gh[2] = {nullptr, nullptr}, *gs = nullptr, *gv[2] = {nullptr, nullptr};
+  float *ggc = nullptr, *gew = nullptr, *gY = nullptr, *gu = nullptr;
+  float4* gr = nullptr;
+  double *atomE = nullptr, *esum = nullptr;
+  std::vector<float*> a_tb, a_edge, x, gam, s, V, e;
+  std::vector<std::vector<float*>> a_lat;
+};
+
+}  // namespace nq
+
+struct nq_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  std::string last_error;
+  nq::NbrList nl;
+  nq::Workspace ws;
+  // MD graph state
+  hipStream_t md_stream = nullptr;
+  hipEvent_t ev[2] = {nullptr, nullptr};
+  hipGraphExec_t graph_exec = nullptr;
+  std::vector<const void*> graph_key;
+  nq::DevBuf md_scratch;
+  int64_t last_edges = 0;
+};
+
+namespace nq {
+
+// ---- neighbour list (neighbor.hip)
+void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin);
+void nbr_build_async(nq_ctx* ctx, const double* pos, bool predicated);
+void nbr_displacement_check_async(nq_ctx* ctx, const double* pos, double half_margin);
+void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut);
+
+// ---- model (model.cpp)
+Dims make_dims(const nq_model_desc& d);
+nq_model* model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* w, int64_t n_w);
+void weight_layout(const nq_model_desc& d, std::vector<std::pair<int64_t, int64_t>>& segs);
+void derive_cg(CGTable& t);
+
+// ---- pipeline (forward.hip / backward.hip)
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms);
+void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64_t n,
+                   double* energy, double* atom_energy);
+void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces);
+
+// ---- MD (md.hip)
+void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass,
+                        int64_t n, double half_dt);
+void md_drift_async(hipStream_t s, double* pos, const double* vel, int64_t n, double dt,
+                    const double box[3]);
+void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n,
+                   double* out);
+
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }
+
+}  // namespace nq

@@ -1,0 +1,849 @@
+// Energy and force pipeline of the Allegro-style edge model (gfx950).
+//
+// The model (paper Sec. 2.1: pairwise embedding energies E_ij within a cutoff,
+// E(3)-equivariant tensors up to rank l, tensor products of irreducible
+// representations; forces f = -dE/dr, Eq. 1) is evaluated as a chain of
+// edge-batched stages over the directed edges sorted by centre atom:
+//   geometry   d, rhat, cutoff u, Bessel basis b, spherical harmonics Y
+//   two-body   MLP on [onehot z_i | onehot z_j | b], x0 = u * h        (matrix cores)
+//   features   [w0 | e1] = x0 [W_V0 | W_env^1]                          (matrix cores)
+//   layer t    Gamma_i = nu^-1/2 sum_k e_ik (x) Y_ik   (one wavefront per centre)
+//              T = C (V (x) Gamma_i), s = scalar paths (one thread per edge-channel)
+//              V_t = mixing of T across channels and paths (t < T)
+//              x_t = (x_{t-1} + u MLP([x_{t-1} | s])) / sqrt2            (matrix cores)
+//              e_{t+1} = x_t W_env^{t+1}                                (matrix cores)
+//   energy     E_ij = sigma_E (SiLU(x_T W_e) w_out); E_i, E (compensated FP64)
+// and then its hand-written adjoint in reverse order, which yields
+// g_ij = dE/dr_ij per edge; the force on atom a is gathered as
+// sum over its edges of g(a,j) - g(j,a) through the reverse-edge index, so no
+// atomics are needed and the result is deterministic.
+#include <cmath>
+
+#include "gemm.hpp"
+#include "nq_internal.hpp"
+
+namespace nq {
+
+namespace {
+
+constexpr int kGeo = 16;  // geo row: d, u, rhat(3), Y(9), pad
+constexpr int kGeoY = 5;
+
+__device__ inline const float* cg_at(const float* cg, int l1, int l2, int l3) {
+  return cg + ((l1 * (kMaxL + 1) + l2) * (kMaxL + 1) + l3) * (2 * kMaxL + 1) * (2 * kMaxL + 1) * (2 * kMaxL + 1);
+}
+__device__ inline float cg_val(const float* t, int m1, int m2, int m3) {
+  return t[(m1 * (2 * kMaxL + 1) + m2) * (2 * kMaxL + 1) + m3];
+}
+
+// Real spherical harmonics, component normalised, order l=1: (x,y,z);
+// l=2: (xy, yz, 3z^2-1, xz, x^2-y^2) with the factors below.
+__device__ inline void sph(float x, float y, float z, float* Y) {
+  const float s3 = 1.7320508075688772f, s5 = 2.2360679774997897f, s15 = 3.872983346207417f;
+  Y[0] = 1.f;
+  Y[1] = s3 * x;
+  Y[2] = s3 * y;
+  Y[3] = s3 * z;
+  Y[4] = s15 * x * y;
+  Y[5] = s15 * y * z;
+  Y[6] = 0.5f * s5 * (3.f * z * z - 1.f);
+  Y[7] = s15 * x * z;
+  Y[8] = 0.5f * s15 * (x * x - y * y);
+}
+
+// Polynomial cutoff u(x) and du/dx, x = d / r_c.
+__device__ inline void envelope(float x, int p, float& u, float& du) {
+  if (x >= 1.f) {
+    u = 0.f;
+    du = 0.f;
+    return;
+  }
+  float xp1 = 1.f;  // x^(p-1)
+  for (int k = 0; k < p - 1; ++k) xp1 *= x;
+  const float xp = xp1 * x;
+  const float c0 = 0.5f * (p + 1) * (p + 2), c1 = (float)(p * (p + 2)), c2 = 0.5f * p * (p + 1);
+  u = 1.f - c0 * xp + c1 * xp * x - c2 * xp * x * x;
+  const float om = 1.f - x;
+  du = -0.5f * p * (p + 1) * (p + 2) * xp1 * om * om;
+}
+
+// ------------------------------------------------------------------ geometry
+__global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __restrict__ rij,
+                           const int* __restrict__ ei, const int* __restrict__ ej,
+                           const int32_t* __restrict__ species, int S, int nb, int p, float rc,
+                           int K0p, float* __restrict__ geo, float* __restrict__ h0, int* __restrict__ flags) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= *nedge_p) return;
+  const float4 r = rij[e];
+  const float d = r.w, inv = 1.f / d;
+  const float x = r.x * inv, y = r.y * inv, z = r.z * inv;
+  float u, du;
+  envelope(d / rc, p, u, du);
+  float Y[9];
+  sph(x, y, z, Y);
+  float* g = geo + e * kGeo;
+  g[0] = d;
+  g[1] = u;
+  g[2] = x;
+  g[3] = y;
+  g[4] = z;
+#pragma unroll
+  for (int k = 0; k < 9; ++k) g[kGeoY + k] = Y[k];
+  g[14] = 0.f;
+  g[15] = 0.f;
+  float* h = h0 + e * K0p;
+  const int zi = species[ei[e]], zj = species[ej[e]];
+  if (zi < 0 || zi >= S || zj < 0 || zj >= S) flags[5] = 1;
+  for (int k = 0; k < S; ++k) {
+    h[k] = (k == zi) ? 1.f : 0.f;
+    h[S + k] = (k == zj) ? 1.f : 0.f;
+  }
+  const float pref = 2.f / rc, w = 3.14159265358979323846f / rc;
+  for (int n = 1; n <= nb; ++n) h[2 * S + n - 1] = pref * sinf(n * w * d) * inv * u;
+  for (int k = 2 * S + nb; k < K0p; ++k) h[k] = 0.f;
+}
+
+// ------------------------------------------------------------------ environment sums
+// One wavefront per centre i; lane = (channel c, group g), group g owns the
+// components lm = g, g+G, ... of Gamma_i[lm][c].
+template <int NY>
+__global__ __launch_bounds__(256) void k_env_fwd(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
+                                                 const float* __restrict__ esrc, int lde,
+                                                 const float* __restrict__ geo, int C, float scale,
+                                                 float* __restrict__ gam) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (i >= n) return;
+  const int lane = threadIdx.x % 64;
+  const int c = lane % C, g = lane / C, G = 64 / C;
+  float acc[NY];
+#pragma unroll
+  for (int q = 0; q < NY; ++q) acc[q] = 0.f;
+  const int ne = *nedge_p;
+  const int b = min(eoff[i], ne), e1 = min(eoff[i + 1], ne);
+  for (int e = b; e < e1; ++e) {
+    const float* Y = geo + (int64_t)e * kGeo + kGeoY;
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+      const int lm = g + q * G;
+      if (lm < NY) {
+        const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+        acc[q] += esrc[(int64_t)e * lde + l * C + c] * Y[lm];
+      }
+    }
+  }
+#pragma unroll
+  for (int q = 0; q < NY; ++q) {
+    const int lm = g + q * G;
+    if (lm < NY) gam[(i * NY + lm) * C + c] = acc[q] * scale;
+  }
+}
+
+// ------------------------------------------------------------------ tensor products
+// Compile-time walk over the coupling paths (l1,l2,l3) of one layer in
+// lexicographic order. `f(l1,l2,l3,toff,qscal,pidx_in_l3)` is called for each
+// path that is needed (all paths, or only l3 == 0 when `scalar_only`); toff is
+// the path's offset in the full list of T components, so all offsets are
+// compile-time constants after unrolling.
+template <int LMAX, class F>
+__device__ inline void for_paths(bool scalar_only, F&& f) {
+  int toff = 0, qs = 0;
+  int pcount[3] = {0, 0, 0};
+#pragma unroll
+  for (int l1 = 0; l1 <= LMAX; ++l1)
+#pragma unroll
+    for (int l2 = 0; l2 <= LMAX; ++l2)
+#pragma unroll
+      for (int l3 = 0; l3 <= LMAX; ++l3) {
+        const bool ok = (l1 - l2 <= l3) && (l2 - l1 <= l3) && (l3 <= l1 + l2) && ((l1 + l2 + l3) % 2 == 0);
+        if (ok) {
+          if (!scalar_only || l3 == 0) f(l1, l2, l3, toff, qs, pcount[l3]);
+          toff += 2 * l3 + 1;
+          if (l3 == 0) qs++;
+          pcount[l3]++;
+        }
+      }
+}
+
+template <int LMAX> struct TPSize {
+  static constexpr int NY = (LMAX + 1) * (LMAX + 1);
+  static constexpr int NT = LMAX == 1 ? 8 : 35;  // sum over paths of (2 l3 + 1)
+};
+
+// Loads V_{t-1}[lm] of edge e, channel c (t = 1: w0[l][c] * Y[lm]).
+template <int NY>
+__device__ inline void load_vprev(bool first, int64_t e, int c, int C, const float* we1, int ldwe,
+                                  const float* vprev, const float* Y, float* V) {
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) {
+    if (first) {
+      const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+      V[lm] = we1[e * ldwe + l * C + c] * Y[lm];
+    } else {
+      V[lm] = vprev[(e * NY + lm) * C + c];
+    }
+  }
+}
+
+// Forward tensor product of one layer: s (scalar paths) and, for t < T, the
+// mixed features V_t. Block = (256 / C) edges x C channels.
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_tp_fwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
+                                                const float* __restrict__ geo, int C, int first, int last,
+                                                const float* __restrict__ we1, int ldwe,
+                                                const float* __restrict__ vprev, const float* __restrict__ gam,
+                                                const float* __restrict__ cg, float* __restrict__ s, int lds,
+                                                const float* __restrict__ mix, float* __restrict__ vout) {
+  constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
+  __shared__ float Tl[256 * NT];
+  const int epb = 256 / C;
+  const int el = threadIdx.x / C, c = threadIdx.x % C;
+  const int64_t e = (int64_t)blockIdx.x * epb + el;
+  const bool valid = e < *nedge_p;
+  float T[NT];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) T[k] = 0.f;
+  if (valid) {
+    const float* Y = geo + e * kGeo + kGeoY;
+    float V[NY], G[NY];
+    load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
+    const int64_t i = ei[e];
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
+    for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int qs, int) {
+      const float* t = cg_at(cg, l1, l2, l3);
+#pragma unroll
+      for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+        float a = 0.f;
+#pragma unroll
+        for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+#pragma unroll
+          for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) a += cg_val(t, m1, m2, m3) * V[l1 * l1 + m1] * G[l2 * l2 + m2];
+        T[toff + m3] = a;
+      }
+      if (l3 == 0) s[e * lds + qs * C + c] = T[toff];
+    });
+  }
+  if (last) return;
+  // channel mixing: V_t[l3 m][c'] = sum_{p in l3} sum_c T_p[m][c] W_l3[(p, c), c']
+#pragma unroll
+  for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * C + c] = T[k];
+  __syncthreads();
+  if (!valid) return;
+  int moff[3];
+  {
+    int o = 0;
+    int cnt[3] = {0, 0, 0};
+    for_paths<LMAX>(false, [&](int, int, int l3, int, int, int) { cnt[l3]++; });
+#pragma unroll
+    for (int l3 = 0; l3 <= LMAX; ++l3) {
+      moff[l3] = o;
+      o += cnt[l3] * C * C;
+    }
+  }
+  float out[NY];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) out[k] = 0.f;
+  for_paths<LMAX>(false, [&](int, int, int l3, int toff, int, int pidx) {
+    const float* W = mix + moff[l3] + (int64_t)pidx * C * C;
+    for (int cc = 0; cc < C; ++cc) {
+      const float w = W[cc * C + c];
+#pragma unroll
+      for (int m = 0; m < 2 * l3 + 1; ++m) out[l3 * l3 + m] += Tl[(el * NT + toff + m) * C + cc] * w;
+    }
+  });
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) vout[(e * NY + lm) * C + c] = out[lm];
+}
+
+// ------------------------------------------------------------------ energy
+// E_ij = sigma_E * sum_k SiLU(a[k]) w_out[k]; 16 lanes per edge.
+__global__ __launch_bounds__(256) void k_edge_energy(const int* __restrict__ nedge_p, const float* __restrict__ a,
+                                                     int lda, int K, const float* __restrict__ wout, float sigma,
+                                                     float* __restrict__ eij) {
+  const int64_t e = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+  const int l = threadIdx.x % 16;
+  float acc = 0.f;
+  const bool valid = e < *nedge_p;
+  if (valid)
+    for (int k = l; k < K; k += 16) acc += siluf(a[e * lda + k]) * wout[k];
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (valid && l == 0) eij[e] = sigma * acc;
+}
+
+__global__ void k_atom_energy(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
+                              const float* __restrict__ eij, double* __restrict__ atomE, double* __restrict__ out) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int ne = *nedge_p;
+  double s = 0.0;
+  for (int e = min(eoff[a], ne); e < min(eoff[a + 1], ne); ++e) s += (double)eij[e];
+  atomE[a] = s;
+  if (out) out[a] = s;
+}
+
+// Neumaier-compensated FP64 sum of n values by one block.
+__global__ __launch_bounds__(1024) void k_total_energy(int64_t n, const double* __restrict__ v,
+                                                       double* __restrict__ energy) {
+  __shared__ double hs[1024], hc[1024];
+  double s = 0.0, c = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double x = v[k];
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  hs[threadIdx.x] = s;
+  hc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double a = hs[threadIdx.x], b = hs[threadIdx.x + o];
+      const double t = a + b;
+      const double err = (fabs(a) >= fabs(b)) ? (a - t) + b : (b - t) + a;
+      hs[threadIdx.x] = t;
+      hc[threadIdx.x] += hc[threadIdx.x + o] + err;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) energy[0] = hs[0] + hc[0];
+}
+
+// ------------------------------------------------------------------ adjoint helpers
+__global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) p[i] = v;
+}
+
+// gu[e] += c * sum_k g[e][k] * SiLU(a[e][k]); 16 lanes per edge.
+__global__ __launch_bounds__(256) void k_rowdot_gu(const int* __restrict__ nedge_p, const float* __restrict__ g,
+                                                   int ldg, const float* __restrict__ a, int lda, int K, float c,
+                                                   float* __restrict__ gu) {
+  const int64_t e = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
+  const int l = threadIdx.x % 16;
+  const bool valid = e < *nedge_p;
+  float acc = 0.f;
+  if (valid)
+    for (int k = l; k < K; k += 16) acc += g[e * ldg + k] * siluf(a[e * lda + k]);
+#pragma unroll
+  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
+  if (valid && l == 0) gu[e] += c * acc;
+}
+
+// Adjoint of one layer's tensor product (and of the channel mixing for t < T).
+// Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i, and either
+// dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and the w0 part
+// of dE/dY into gY.
+template <int LMAX>
+__global__ __launch_bounds__(256) void k_tp_bwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
+                                                const float* __restrict__ geo, int C, int first, int last,
+                                                const float* __restrict__ we1, int ldwe,
+                                                const float* __restrict__ vprev, const float* __restrict__ gam,
+                                                const float* __restrict__ cg, const float* __restrict__ gs,
+                                                int ldgs, const float* __restrict__ gvin,
+                                                const float* __restrict__ mix, float* __restrict__ ggc,
+                                                float* __restrict__ gvout, float* __restrict__ gew, int ldgew,
+                                                float* __restrict__ gY) {
+  constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
+  __shared__ float gVl[256 * NY];
+  const int epb = 256 / C;
+  const int el = threadIdx.x / C, c = threadIdx.x % C;
+  const int64_t e = (int64_t)blockIdx.x * epb + el;
+  const bool valid = e < *nedge_p;
+  if (!last) {
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * C + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
+    __syncthreads();
+  }
+  if (!valid) return;
+  const float* Y = geo + e * kGeo + kGeoY;
+  float V[NY], G[NY], gT[NT];
+  load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
+  const int64_t i = ei[e];
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
+#pragma unroll
+  for (int k = 0; k < NT; ++k) gT[k] = 0.f;
+  int moff[3] = {0, 0, 0};
+  {
+    int o = 0;
+    int cnt[3] = {0, 0, 0};
+    for_paths<LMAX>(false, [&](int, int, int l3, int, int, int) { cnt[l3]++; });
+#pragma unroll
+    for (int l3 = 0; l3 <= LMAX; ++l3) {
+      moff[l3] = o;
+      o += cnt[l3] * C * C;
+    }
+  }
+  for_paths<LMAX>(last, [&](int, int, int l3, int toff, int qs, int pidx) {
+    if (l3 == 0) gT[toff] += gs[e * ldgs + qs * C + c];
+    if (!last) {
+      const float* W = mix + moff[l3] + (int64_t)pidx * C * C + (int64_t)c * C;
+      for (int cc = 0; cc < C; ++cc) {
+        const float w = W[cc];
+#pragma unroll
+        for (int m = 0; m < 2 * l3 + 1; ++m) gT[toff + m] += gVl[(el * NY + l3 * l3 + m) * C + cc] * w;
+      }
+    }
+  });
+  float gV[NY], gG[NY];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
+    gV[k] = 0.f;
+    gG[k] = 0.f;
+  }
+  for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int, int) {
+    const float* t = cg_at(cg, l1, l2, l3);
+#pragma unroll
+    for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+      const float g = gT[toff + m3];
+#pragma unroll
+      for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+#pragma unroll
+        for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+          const float w = cg_val(t, m1, m2, m3) * g;
+          gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
+          gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
+        }
+    }
+  });
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) ggc[(e * NY + lm) * C + c] = gG[lm];
+  if (!first) {
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) gvout[(e * NY + lm) * C + c] = gV[lm];
+    return;
+  }
+  // V0[c][lm] = w0[l][c] Y[lm]
+#pragma unroll
+  for (int l = 0; l <= LMAX; ++l) {
+    float gw = 0.f;
+    const float w0 = we1[e * ldwe + l * C + c];
+#pragma unroll
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      gw += gV[l * l + m] * Y[l * l + m];
+      float part = w0 * gV[l * l + m];
+      for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
+      if (c == 0) gY[e * 16 + l * l + m] += part;
+    }
+    gew[e * ldgew + l * C + c] = gw;
+  }
+}
+
+// Per-centre adjoint of the environment sum: dGamma_i = nu^-1/2 sum_j ggc[j];
+// then for each edge k of i: de_k[l][c] = sum_m dGamma_i[lm][c] Y_k[lm] and
+// dY_k[lm] += sum_c e_k[l][c] dGamma_i[lm][c].
+template <int NY>
+__global__ __launch_bounds__(256) void k_env_bwd(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
+                                                 const float* __restrict__ ggc, const float* __restrict__ esrc,
+                                                 int lde, const float* __restrict__ geo, int C, float scale,
+                                                 float* __restrict__ gew, int ldgew, int gcol,
+                                                 float* __restrict__ gY) {
+  const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
+  if (i >= n) return;
+  const int lane = threadIdx.x % 64;
+  const int c = lane % C, g = lane / C, G = 64 / C;
+  constexpr int L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
+  float acc[NY];
+#pragma unroll
+  for (int q = 0; q < NY; ++q) acc[q] = 0.f;
+  const int ne = *nedge_p;
+  const int b = min(eoff[i], ne), e1 = min(eoff[i + 1], ne);
+  for (int e = b; e < e1; ++e)
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+      const int lm = g + q * G;
+      if (lm < NY) acc[q] += ggc[((int64_t)e * NY + lm) * C + c];
+    }
+#pragma unroll
+  for (int q = 0; q < NY; ++q) acc[q] *= scale;
+  for (int e = b; e < e1; ++e) {
+    const float* Y = geo + (int64_t)e * kGeo + kGeoY;
+    float part[L + 1];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) part[l] = 0.f;
+#pragma unroll
+    for (int q = 0; q < NY; ++q) {
+      const int lm = g + q * G;
+      if (lm < NY) {
+        const float y = Y[lm];
+        const int lq = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+#pragma unroll
+        for (int l = 0; l <= L; ++l)
+          if (l == lq) part[l] += acc[q] * y;
+        // dY contribution, reduced over the channels of this group
+        float prod = esrc[(int64_t)e * lde + lq * C + c] * acc[q];
+        for (int o = C / 2; o >= 1; o >>= 1) prod += __shfl_xor(prod, o, C);
+        if (c == 0) gY[(int64_t)e * 16 + lm] += prod;
+      }
+    }
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+      float v = part[l];
+      for (int o = C; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
+      if (g == 0) gew[(int64_t)e * ldgew + gcol + l * C + c] = v;
+    }
+  }
+}
+
+__device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, float& gx, float& gy, float& gz) {
+  const float s3 = 1.7320508075688772f, s5 = 2.2360679774997897f, s15 = 3.872983346207417f;
+  gx = s3 * gY[1] + s15 * (y * gY[4] + z * gY[7] + x * gY[8]);
+  gy = s3 * gY[2] + s15 * (x * gY[4] + z * gY[5] - y * gY[8]);
+  gz = s3 * gY[3] + s15 * (y * gY[5] + x * gY[7]) + 3.f * s5 * z * gY[6];
+}
+
+// Adjoint of the edge geometry: dE/dr_ij from dE/du, dE/dY and dE/db.
+__global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __restrict__ geo,
+                               const float* __restrict__ gu, const float* __restrict__ gYb,
+                               const float* __restrict__ gh0, int ldh0, int boff, int nb, int p, float rc, int NY,
+                               float4* __restrict__ gr) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= *nedge_p) return;
+  const float* g = geo + e * kGeo;
+  const float d = g[0], x = g[2], y = g[3], z = g[4];
+  float u, dudx;
+  envelope(d / rc, p, u, dudx);
+  float gut = gu[e], gd = 0.f;
+  const float pref = 2.f / rc, w = 3.14159265358979323846f / rc, inv = 1.f / d;
+  for (int n = 1; n <= nb; ++n) {
+    const float k = n * w;
+    float sn, cs;
+    sincosf(k * d, &sn, &cs);
+    const float B = pref * sn * inv;
+    const float dB = pref * (k * cs * inv - sn * inv * inv);
+    const float gb = gh0[e * ldh0 + boff + n - 1];
+    gut += gb * B;
+    gd += gb * u * dB;
+  }
+  gd += gut * dudx / rc;
+  float gY[9];
+#pragma unroll
+  for (int k = 0; k < 9; ++k) gY[k] = (k < NY) ? gYb[e * 16 + k] : 0.f;
+  float ax, ay, az;
+  sph_grad_dot(gY, x, y, z, ax, ay, az);
+  const float rad = ax * x + ay * y + az * z;
+  gr[e] = make_float4(gd * x + (ax - rad * x) * inv, gd * y + (ay - rad * y) * inv, gd * z + (az - rad * z) * inv,
+                      0.f);
+}
+
+// F_a = sum over edges (a, j): g(a,j) - g(j,a)   (F_i += g_ij, F_j -= g_ij)
+__global__ void k_forces(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
+                         const int* __restrict__ rev, const float4* __restrict__ gr, double* __restrict__ F) {
+  const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (a >= n) return;
+  const int ne = *nedge_p;
+  double fx = 0, fy = 0, fz = 0;
+  for (int e = min(eoff[a], ne); e < min(eoff[a + 1], ne); ++e) {
+    const int r = rev[e];
+    const float4 g = gr[e], h = (r < ne) ? gr[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+    fx += (double)g.x - (double)h.x;
+    fy += (double)g.y - (double)h.y;
+    fz += (double)g.z - (double)h.z;
+  }
+  F[3 * a] = fx;
+  F[3 * a + 1] = fy;
+  F[3 * a + 2] = fz;
+}
+
+// ------------------------------------------------------------------ GEMM dispatch
+template <typename T, int BM, int NP, int WM, int WN>
+void launch_gemm_t(hipStream_t s, int64_t cap, int Kp, const T* Bt, const int* nrows, const ALoad& ld,
+                   const Epi& ep) {
+  k_gemm<T, BM, NP, WM, WN><<<(unsigned)cdiv(cap, BM), 256, 0, s>>>(Kp, Bt, nrows, ld, ep);
+}
+
+template <typename T>
+void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const T* Bt, const int* nrows, const ALoad& ld,
+                    const Epi& ep) {
+  switch (NP) {
+    case 16: launch_gemm_t<T, 128, 16, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 32: launch_gemm_t<T, 128, 32, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 48: launch_gemm_t<T, 128, 48, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 64: launch_gemm_t<T, 128, 64, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 96: launch_gemm_t<T, 128, 96, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 128: launch_gemm_t<T, 128, 128, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 192: launch_gemm_t<T, 128, 192, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 256: launch_gemm_t<T, 128, 256, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 352: launch_gemm_t<T, 64, 352, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 384: launch_gemm_t<T, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 512: launch_gemm_t<T, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 704: launch_gemm_t<T, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    default: throw Error{NQ_ERR_UNSUPPORTED, "no matrix-core kernel for output width " + std::to_string(NP)};
+  }
+}
+
+// y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map.
+void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep) {
+  const Workspace& ws = ctx->ws;
+  const int NP = bwd ? L.np_b : L.np_f;
+  const int Kp = bwd ? L.kp_b : L.kp_f;
+  if (m->dims.prec == NQ_PRECISION_BF16)
+    launch_gemm_np<bf16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).as<bf16>(), ws.nedge.as<int>(),
+                         ld, ep);
+  else
+    launch_gemm_np<float>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).as<float>(),
+                          ws.nedge.as<int>(), ld, ep);
+  NQ_HIP(hipGetLastError());
+}
+
+ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
+ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
+ALoad a_cat(const float* p, int ld, int K, const float* q, int ldq, int Kq) {
+  return ALoad{A_CAT, p, ld, K, q, ldq, Kq, nullptr, 0, 1.f};
+}
+ALoad a_gradsilu(const float* g, int ldg, int K, const float* a, int lda, const float* rs, float c) {
+  return ALoad{A_GRADSILU, g, ldg, K, a, lda, 0, rs, kGeo, c};
+}
+Epi e_store(float* o, int ld, int N) { return Epi{E_STORE, o, ld, N, nullptr, 0, nullptr, 0, nullptr, 0, 0}; }
+Epi e_add(float* o, int ld, int N) { return Epi{E_ADD, o, ld, N, nullptr, 0, nullptr, 0, nullptr, 0, 0}; }
+
+unsigned grid_for(int64_t n, int per_block) { return (unsigned)std::max<int64_t>(1, cdiv(n, per_block)); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ workspace
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms) {
+  Workspace& ws = ctx->ws;
+  cap = rup(std::max<int64_t>(cap, 1), 128);
+  if (ws.model == m && ws.cap >= cap && ws.n_atoms == n_atoms) return;
+  const Dims& d = m->dims;
+  NQ_HIP(hipStreamSynchronize(ctx->stream));
+  ws.bufs.clear();
+  ws.cap = cap;
+  ws.n_atoms = n_atoms;
+  ws.model = m;
+  ws.ecnt.ensure(n_atoms * 4);
+  ws.eoff.ensure((n_atoms + 1) * 4);
+  ws.ei.ensure(cap * 4);
+  ws.ej.ensure(cap * 4);
+  ws.rev.ensure(cap * 4);
+  ws.rij.ensure(cap * 16);
+  ws.nedge.ensure(64);
+  auto fbuf = [&](int64_t rows, int64_t width) -> float* {
+    ws.bufs.emplace_back(new DevBuf());
+    ws.bufs.back()->ensure((size_t)rows * width * 4);
+    return ws.bufs.back()->as<float>();
+  };
+  ws.K0p = (int)rup(d.n_in2b, 32);
+  int maxw = d.n_in2b;
+  for (int k = 0; k < d.n_tb; ++k) maxw = std::max(maxw, d.tb[k]);
+  for (int k = 0; k < d.n_lat; ++k) maxw = std::max(maxw, d.lat[k]);
+  for (int k = 0; k < d.n_edge; ++k) maxw = std::max(maxw, d.edge[k]);
+  maxw = std::max(maxw, d.D + d.nscal * d.C);
+  ws.maxw = (int)rup(maxw, 16);
+  ws.geo = fbuf(cap, kGeo);
+  ws.h0 = fbuf(cap, ws.K0p);
+  ws.a_tb.clear();
+  for (int k = 0; k < d.n_tb; ++k) ws.a_tb.push_back(fbuf(cap, d.tb[k]));
+  ws.we1 = fbuf(cap, 2 * d.NW);
+  ws.x.assign(d.T + 1, nullptr);
+  ws.gam.assign(d.T + 1, nullptr);
+  ws.s.assign(d.T + 1, nullptr);
+  ws.V.assign(d.T + 1, nullptr);
+  ws.e.assign(d.T + 1, nullptr);
+  ws.a_lat.assign(d.T + 1, {});
+  ws.x[0] = fbuf(cap, d.D);
+  for (int t = 1; t <= d.T; ++t) {
+    if (t > 1) ws.e[t] = fbuf(cap, d.NW);
+    ws.gam[t] = fbuf(n_atoms, d.NY * d.C);
+    ws.s[t] = fbuf(cap, d.nscal * d.C);
+    for (int k = 0; k < d.n_lat; ++k) ws.a_lat[t].push_back(fbuf(cap, d.lat[k]));
+    ws.x[t] = fbuf(cap, d.D);
+    if (t < d.T) ws.V[t] = fbuf(cap, d.NY * d.C);
+  }
+  ws.a_edge.clear();
+  for (int k = 0; k < d.n_edge; ++k) ws.a_edge.push_back(fbuf(cap, d.edge[k]));
+  ws.eij = fbuf(cap, 1);
+  ws.bufs.emplace_back(new DevBuf());
+  ws.bufs.back()->ensure((size_t)n_atoms * 8);
+  ws.atomE = ws.bufs.back()->as<double>();
+  ws.bufs.emplace_back(new DevBuf());
+  ws.bufs.back()->ensure(64);
+  ws.esum = ws.bufs.back()->as<double>();
+  ws.gx = fbuf(cap, d.D);
+  ws.gh[0] = fbuf(cap, ws.maxw);
+  ws.gh[1] = fbuf(cap, ws.maxw);
+  ws.gs = fbuf(cap, d.nscal * d.C);
+  ws.gv[0] = fbuf(cap, d.NY * d.C);
+  ws.gv[1] = fbuf(cap, d.NY * d.C);
+  ws.ggc = fbuf(cap, d.NY * d.C);
+  ws.gew = fbuf(cap, 2 * d.NW);
+  ws.gY = fbuf(cap, 16);
+  ws.gu = fbuf(cap, 1);
+  ws.gr = reinterpret_cast<float4*>(fbuf(cap, 4));
+}
+
+// ------------------------------------------------------------------ forward
+void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64_t n, double* energy,
+                   double* atom_energy) {
+  const Dims& d = m->dims;
+  Workspace& ws = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int* ne = ws.nedge.as<int>();
+  const int64_t cap = ws.cap;
+  const float* u = ws.geo + 1;
+  k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.rij.as<float4>(), ws.ei.as<int>(), ws.ej.as<int>(),
+                                                      species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
+                                                 ctx->nl.flags.as<int>());
+  // two-body MLP; the last layer stores x0 = u * SiLU(a)
+  for (int k = 0; k < d.n_tb; ++k) {
+    const Lin& L = *m->tb[k];
+    ALoad ld = k == 0 ? a_plain(ws.h0, ws.K0p, d.n_in2b) : a_silu(ws.a_tb[k - 1], d.tb[k - 1], d.tb[k - 1]);
+    Epi ep = e_store(ws.a_tb[k], d.tb[k], d.tb[k]);
+    if (k == d.n_tb - 1) {
+      ep.mode = E_STORE_X0;
+      ep.o1 = ws.x[0];
+      ep.ld1 = d.D;
+      ep.rs = u;
+      ep.rs_ld = kGeo;
+    }
+    gemm(ctx, m, L, false, ld, ep);
+  }
+  gemm(ctx, m, m->v0e1, false, a_plain(ws.x[0], d.D, d.D), e_store(ws.we1, 2 * d.NW, 2 * d.NW));
+  const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
+  for (int t = 1; t <= d.T; ++t) {
+    const bool last = t == d.T;
+    if (t > 1) gemm(ctx, m, *m->env[t - 1], false, a_plain(ws.x[t - 1], d.D, d.D), e_store(ws.e[t], d.NW, d.NW));
+    const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
+    const int lde = t == 1 ? 2 * d.NW : d.NW;
+    if (d.L == 1)
+      k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+                                                        ws.gam[t]);
+    else
+      k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+                                                        ws.gam[t]);
+    const int epb = 256 / d.C;
+    const float* mix = last ? nullptr : m->mix.as<float>() + m->mix_off[t - 1];
+    if (d.L == 1)
+      k_tp_fwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
+                                                           ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+    else
+      k_tp_fwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
+                                                           ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+    NQ_HIP(hipGetLastError());
+    // latent MLP on [x | s]; the last layer applies the residual update
+    for (int k = 0; k < d.n_lat; ++k) {
+      const Lin& L = *m->lat[t - 1][k];
+      ALoad ld = k == 0 ? a_cat(ws.x[t - 1], d.D, d.D, ws.s[t], d.nscal * d.C, d.nscal * d.C)
+                        : a_silu(ws.a_lat[t][k - 1], d.lat[k - 1], d.lat[k - 1]);
+      Epi ep = e_store(ws.a_lat[t][k], d.lat[k], d.lat[k]);
+      if (k == d.n_lat - 1) {
+        ep.mode = E_RESIDUAL;
+        ep.o1 = ws.x[t];
+        ep.ld1 = d.D;
+        ep.x = ws.x[t - 1];
+        ep.ldx = d.D;
+        ep.rs = u;
+        ep.rs_ld = kGeo;
+      }
+      gemm(ctx, m, L, false, ld, ep);
+    }
+  }
+  for (int k = 0; k < d.n_edge; ++k) {
+    ALoad ld = k == 0 ? a_plain(ws.x[d.T], d.D, d.D) : a_silu(ws.a_edge[k - 1], d.edge[k - 1], d.edge[k - 1]);
+    gemm(ctx, m, *m->edge[k], false, ld, e_store(ws.a_edge[k], d.edge[k], d.edge[k]));
+  }
+  const int ke = d.n_edge - 1;
+  k_edge_energy<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.a_edge[ke], d.edge[ke], d.edge[ke],
+                                                        m->wout.as<float>(), (float)d.sigma_e, ws.eij);
+  k_atom_energy<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.eij, ws.atomE, atom_energy);
+  k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+  NQ_HIP(hipGetLastError());
+}
+
+// ------------------------------------------------------------------ adjoint
+void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
+  const Dims& d = m->dims;
+  Workspace& ws = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int* ne = ws.nedge.as<int>();
+  const int64_t cap = ws.cap;
+  const float* u = ws.geo + 1;
+  k_fill<<<grid_for(cap, 256), 256, 0, s>>>(ws.gu, cap, 0.f);
+  k_fill<<<grid_for(cap * 16, 256), 256, 0, s>>>(ws.gY, cap * 16, 0.f);
+  // edge MLP: g_a(last) = sigma_E w_out SiLU'(a)
+  {
+    float* gout = nullptr;
+    for (int k = d.n_edge - 1; k >= 0; --k) {
+      ALoad ld = k == d.n_edge - 1
+                     ? a_gradsilu(m->wout.as<float>(), 0, d.edge[k], ws.a_edge[k], d.edge[k], nullptr,
+                                  (float)d.sigma_e)
+                     : a_gradsilu(gout, ws.maxw, d.edge[k], ws.a_edge[k], d.edge[k], nullptr, 1.f);
+      const int fin = k == 0 ? d.D : d.edge[k - 1];
+      float* dst = k == 0 ? ws.gx : ws.gh[k % 2];
+      gemm(ctx, m, *m->edge[k], true, ld, e_store(dst, k == 0 ? d.D : ws.maxw, fin));
+      gout = dst;
+    }
+  }
+  const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
+  int gvcur = 0;  // ws.gv[gvcur] holds dE/dV_t while processing layer t (t < T)
+  for (int t = d.T; t >= 1; --t) {
+    const bool last = t == d.T;
+    const int kl = d.n_lat - 1;
+    k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_lat[t][kl], d.lat[kl], d.D, kInvSqrt2,
+                                                        ws.gu);
+    float* gout = nullptr;
+    for (int k = kl; k >= 0; --k) {
+      ALoad ld = k == kl ? a_gradsilu(ws.gx, d.D, d.lat[k], ws.a_lat[t][k], d.lat[k], u, kInvSqrt2)
+                         : a_gradsilu(gout, ws.maxw, d.lat[k], ws.a_lat[t][k], d.lat[k], nullptr, 1.f);
+      Epi ep;
+      if (k == 0) {
+        ep = Epi{E_LATENT_BWD, ws.gx, d.D, d.D + d.nscal * d.C, ws.gs, d.nscal * d.C, nullptr, 0, nullptr, 0, d.D};
+      } else {
+        ep = e_store(ws.gh[k % 2], ws.maxw, d.lat[k - 1]);
+      }
+      gemm(ctx, m, *m->lat[t - 1][k], true, ld, ep);
+      gout = ws.gh[k % 2];
+    }
+    // tensor-product adjoint
+    const int epb = 256 / d.C;
+    const float* mix = last ? nullptr : m->mix.as<float>() + m->mix_off[t - 1];
+    const float* gvin = last ? nullptr : ws.gv[gvcur];
+    float* gvout = ws.gv[1 - gvcur];
+    if (d.L == 1)
+      k_tp_bwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
+                                                           d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
+                                                           ws.gY);
+    else
+      k_tp_bwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
+                                                           d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
+                                                           ws.gY);
+    gvcur = 1 - gvcur;
+    // environment-sum adjoint -> gew[:, NW:2NW], gY
+    const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
+    const int lde = t == 1 ? 2 * d.NW : d.NW;
+    if (d.L == 1)
+      k_env_bwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
+                                                        inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+    else
+      k_env_bwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
+                                                        inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+    NQ_HIP(hipGetLastError());
+    if (t > 1)
+      gemm(ctx, m, *m->env[t - 1], true, a_plain(ws.gew + d.NW, 2 * d.NW, d.NW), e_add(ws.gx, d.D, d.D));
+    else
+      gemm(ctx, m, m->v0e1, true, a_plain(ws.gew, 2 * d.NW, 2 * d.NW), e_add(ws.gx, d.D, d.D));
+  }
+  // two-body MLP: x0 = u SiLU(a_last)
+  const int kt = d.n_tb - 1;
+  k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_tb[kt], d.tb[kt], d.D, 1.f, ws.gu);
+  float* gout = nullptr;
+  for (int k = kt; k >= 0; --k) {
+    ALoad ld = k == kt ? a_gradsilu(ws.gx, d.D, d.tb[k], ws.a_tb[k], d.tb[k], u, 1.f)
+                       : a_gradsilu(gout, ws.maxw, d.tb[k], ws.a_tb[k], d.tb[k], nullptr, 1.f);
+    const int fin = k == 0 ? d.n_in2b : d.tb[k - 1];
+    gemm(ctx, m, *m->tb[k], true, ld, e_store(ws.gh[k % 2], ws.maxw, fin));
+    gout = ws.gh[k % 2];
+  }
+  k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
+                                                          d.p, (float)d.rc, d.NY, ws.gr);
+  k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr, forces);
+  NQ_HIP(hipGetLastError());
+}
+
+}  // namespace nq

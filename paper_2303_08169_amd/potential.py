@@ -1,0 +1,145 @@
+"""PyTorch-facing wrapper of the HIP library.
+
+PyTorch provides device memory and the stream; every step of the energy/force
+path runs in libnnqmd.so. `Potential.energy_forces` returns E and F = -dE/dr
+(paper Sec. 2.1, Eq. 1); `EnergyForces` exposes E to autograd with the
+library's forces as its gradient; `Potential.step` runs velocity-Verlet steps
+replayed from a HIP graph.
+"""
+from __future__ import annotations
+
+import ctypes as C
+
+import numpy as np
+import torch
+
+from . import binding as B
+
+
+def _ptr(t: torch.Tensor):
+    return C.c_void_p(t.data_ptr()) if t is not None else None
+
+
+def _cell(box):
+    b = np.broadcast_to(np.asarray(box, dtype=np.float64), (3,)).copy()
+    return (C.c_double * 3)(*b.tolist())
+
+
+class Potential:
+    """One context + one model on a GPU.
+
+    model: an object with the hyper-parameters (n_species, n_bessel, poly_p, lmax,
+    n_layers, channels, twobody, latent, edge, r_cut, avg_num_neighbors,
+    energy_scale); weights: flat FP64 host array in the library's layout.
+    """
+
+    def __init__(self, model, weights, precision: str = "fp32", device: int = 0):
+        if not torch.cuda.is_available():
+            raise RuntimeError("a ROCm GPU is required")
+        self.lib = B.lib()
+        self.device = torch.device("cuda", device)
+        self.desc = B.make_desc(model, precision)
+        self.precision = precision
+        segs, ntot = B.weight_layout(self.desc)
+        w = np.ascontiguousarray(np.asarray(weights, dtype=np.float64))
+        if w.size != ntot:
+            raise ValueError(f"weights have {w.size} values, the model needs {ntot}")
+        self._ctx = C.c_void_p()
+        with torch.cuda.device(self.device):
+            stream = torch.cuda.current_stream(self.device).cuda_stream
+            B.check(self.lib.nq_ctx_create(device, C.c_void_p(stream), C.byref(self._ctx)))
+            self._model = C.c_void_p()
+            B.check(self.lib.nq_model_create(self._ctx, C.byref(self.desc),
+                                             w.ctypes.data_as(C.POINTER(C.c_double)), w.size,
+                                             C.byref(self._model)), self._ctx)
+        self._energy = torch.zeros(1, dtype=torch.float64, device=self.device)
+
+    def close(self):
+        if getattr(self, "_model", None):
+            self.lib.nq_model_destroy(self._model)
+            self._model = None
+        if getattr(self, "_ctx", None):
+            self.lib.nq_ctx_destroy(self._ctx)
+            self._ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _sync_stream(self):
+        s = torch.cuda.current_stream(self.device).cuda_stream
+        B.check(self.lib.nq_ctx_set_stream(self._ctx, C.c_void_p(s)), self._ctx)
+
+    def _check_inputs(self, pos, species):
+        if pos.device != self.device or species.device != self.device:
+            raise ValueError("positions and species must live on the potential's device")
+        if pos.dtype != torch.float64 or species.dtype != torch.int32:
+            raise TypeError("positions must be float64 and species int32")
+        if pos.dim() != 2 or pos.shape[1] != 3 or species.shape != (pos.shape[0],):
+            raise ValueError("positions [n, 3], species [n]")
+        if not (pos.is_contiguous() and species.is_contiguous()):
+            raise ValueError("inputs must be contiguous")
+
+    def neighbor_build(self, pos, box, r_cut=None, skin=1.0):
+        self._sync_stream()
+        rc = float(self.desc.r_cut if r_cut is None else r_cut)
+        B.check(self.lib.nq_neighbor_build(self._ctx, _ptr(pos), pos.shape[0], _cell(box), rc, float(skin)),
+                self._ctx)
+
+    def energy_forces(self, pos, species, box, forces=None, energy=None, atom_energy=False):
+        """(E [1] f64, F [n,3] f64[, E_i [n] f64]) on the device, queued on the current stream."""
+        self._check_inputs(pos, species)
+        n = pos.shape[0]
+        F = forces if forces is not None else torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        E = energy if energy is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        Ei = torch.empty(n, dtype=torch.float64, device=self.device) if atom_energy else None
+        self._sync_stream()
+        B.check(self.lib.nq_energy_forces(self._ctx, self._model, _ptr(pos), _ptr(species), n, _cell(box),
+                                          _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
+        return (E, F, Ei) if atom_energy else (E, F)
+
+    def step(self, pos, vel, inv_mass, species, box, dt_fs, n_steps, forces, epot=None, ekin=None):
+        """n_steps velocity-Verlet steps in place; forces must hold F(pos) on entry."""
+        self._check_inputs(pos, species)
+        self._sync_stream()
+        B.check(self.lib.nq_step(self._ctx, self._model, _ptr(pos), _ptr(vel), _ptr(inv_mass), _ptr(species),
+                                 pos.shape[0], _cell(box), float(dt_fs), int(n_steps), _ptr(forces),
+                                 _ptr(epot), _ptr(ekin)), self._ctx)
+
+    def stats(self):
+        ne, nr = C.c_int64(0), C.c_int64(0)
+        B.check(self.lib.nq_stats(self._ctx, C.byref(ne), C.byref(nr)), self._ctx)
+        return ne.value, nr.value
+
+    def edges(self):
+        ne, _ = self.stats()
+        cap = max(ne, 1)
+        ei = torch.empty(cap, dtype=torch.int32, device=self.device)
+        ej = torch.empty(cap, dtype=torch.int32, device=self.device)
+        n = C.c_int64(0)
+        B.check(self.lib.nq_edges_export(self._ctx, _ptr(ei), _ptr(ej), cap, C.byref(n)), self._ctx)
+        return ei[:n.value], ej[:n.value]
+
+    def debug(self, name: str, cap: int):
+        out = torch.empty(cap, dtype=torch.float32, device=self.device)
+        rows, width = C.c_int64(0), C.c_int64(0)
+        B.check(self.lib.nq_debug_export(self._ctx, self._model, name.encode(), _ptr(out), cap,
+                                         C.byref(rows), C.byref(width)), self._ctx)
+        return out[:rows.value * width.value].view(rows.value, width.value)
+
+
+class EnergyForces(torch.autograd.Function):
+    """E(pos) with dE/dpos = -F from the library's hand-written adjoint."""
+
+    @staticmethod
+    def forward(ctx, pos, potential: Potential, species, box):
+        E, F = potential.energy_forces(pos.detach(), species, box)
+        ctx.save_for_backward(F)
+        return E
+
+    @staticmethod
+    def backward(ctx, gE):
+        (F,) = ctx.saved_tensors
+        return -gE * F, None, None, None
