@@ -47,7 +47,7 @@ typedef enum {
   NQ_ERR_OOM = -6           /* device allocation failed */
 } nq_status;
 
-enum { NQ_PRECISION_FP32 = 0, NQ_PRECISION_BF16 = 1 };
+enum { NQ_PRECISION_FP32 = 0, NQ_PRECISION_BF16 = 1, NQ_PRECISION_BF16X3 = 2 };
 
 typedef struct nq_ctx nq_ctx;
 typedef struct nq_model nq_model;
@@ -55,9 +55,12 @@ typedef struct nq_model nq_model;
 /* Model hyper-parameters. Widths of MLP layers are listed without the input
  * width; twobody[n_twobody-1] is the latent width D and latent[n_latent-1] must
  * equal D. lmax <= 2. n_species <= 8. precision selects the arithmetic of the
- * per-edge MLP products: NQ_PRECISION_FP32 (FP32 everywhere) or
- * NQ_PRECISION_BF16 (BF16 operands on the matrix cores with FP32 accumulation;
- * tensor products, reductions and everything else stay FP32/FP64). */
+ * per-edge MLP products: NQ_PRECISION_FP32 (FP32 operands on the matrix cores),
+ * NQ_PRECISION_BF16 (BF16 operands on the matrix cores, FP32 accumulation) or
+ * NQ_PRECISION_BF16X3 (each FP32 operand split into BF16 hi + lo parts and the
+ * product formed as hi*hi + lo*hi + hi*lo on the matrix cores, FP32
+ * accumulation: about FP32 accuracy at three BF16 products' cost). Tensor
+ * products, reductions and everything else stay FP32/FP64 in every mode. */
 typedef struct {
   int32_t n_species, n_bessel, poly_p, lmax, n_layers, channels;
   int32_t n_twobody, twobody[4];
@@ -139,6 +142,17 @@ nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, in
  * "g" (dE/dr_ij). For parity tests of single stages. Synchronises the stream. */
 nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
                           int64_t cap, int64_t* rows, int64_t* width);
+
+/* Per-kernel timing. While enabled, every kernel launch of nq_energy_forces
+ * (not of nq_step's graph) is bracketed by HIP events recorded on the
+ * context's stream. nq_timing_report synchronises the stream and writes a JSON
+ * object {"n_edges": E, "kernels": [{"name", "count", "ms_total",
+ * "flop_per_launch", "bytes_per_launch"}...]} (algorithmic FLOPs and bytes of
+ * one launch at the last edge count) into buf[cap] (host), then clears the
+ * record. *len (host) receives the length; NQ_ERR_CAPACITY if buf is too
+ * small. */
+nq_status nq_timing(nq_ctx* ctx, int enable);
+nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len);
 
 const char* nq_status_str(nq_status status);
 const char* nq_last_error(const nq_ctx* ctx);

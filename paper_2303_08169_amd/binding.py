@@ -15,11 +15,12 @@ LIB_PATH = os.path.join(HERE, "libnnqmd.so")
 NQ_OK = 0
 STATUS = {0: "NQ_OK", -1: "NQ_ERR_ARG", -2: "NQ_ERR_UNSUPPORTED", -3: "NQ_ERR_CAPACITY",
           -4: "NQ_ERR_NUMERIC", -5: "NQ_ERR_DEVICE", -6: "NQ_ERR_OOM"}
-PRECISION = {"fp32": 0, "bf16": 1}
+PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 EXPORTS = ["nq_ctx_create", "nq_ctx_set_stream", "nq_ctx_destroy", "nq_model_weight_layout",
            "nq_model_create", "nq_model_destroy", "nq_neighbor_build", "nq_energy_forces", "nq_step",
-           "nq_stats", "nq_edges_export", "nq_debug_export", "nq_status_str", "nq_last_error"]
+           "nq_stats", "nq_edges_export", "nq_debug_export", "nq_timing", "nq_timing_report",
+           "nq_status_str", "nq_last_error"]
 
 
 class NQError(RuntimeError):
@@ -84,6 +85,8 @@ def lib():
         "nq_stats": (C.c_int, [vp, P(i64), P(i64)]),
         "nq_edges_export": (C.c_int, [vp, vp, vp, i64, P(i64)]),
         "nq_debug_export": (C.c_int, [vp, vp, C.c_char_p, vp, i64, P(i64), P(i64)]),
+        "nq_timing": (C.c_int, [vp, C.c_int]),
+        "nq_timing_report": (C.c_int, [vp, C.c_char_p, i64, P(i64)]),
         "nq_status_str": (C.c_char_p, [C.c_int]),
         "nq_last_error": (C.c_char_p, [vp]),
     }

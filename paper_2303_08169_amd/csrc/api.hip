@@ -12,6 +12,41 @@ void md_record_async(hipStream_t s, const double* epot_now, const double* ekin_n
 void md_set_int_async(hipStream_t s, int* p, int v);
 }  // namespace nq
 
+namespace nq {
+
+static hipEvent_t pool_event(nq_ctx* ctx) {
+  if (!ctx->event_pool.empty()) {
+    hipEvent_t e = ctx->event_pool.back();
+    ctx->event_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  NQ_HIP(hipEventCreate(&e));
+  return e;
+}
+
+int span_begin(nq_ctx* ctx, const std::string& name, double fpe, double bpe, double fpa, double bpa) {
+  if (!ctx->timing) return -1;
+  Span s;
+  s.name = name;
+  s.a = pool_event(ctx);
+  s.b = pool_event(ctx);
+  s.flop_per_edge = fpe;
+  s.byte_per_edge = bpe;
+  s.flop_per_atom = fpa;
+  s.byte_per_atom = bpa;
+  NQ_HIP(hipEventRecord(s.a, ctx->stream));
+  ctx->spans.push_back(s);
+  return (int)ctx->spans.size() - 1;
+}
+
+void span_end(nq_ctx* ctx, int idx) {
+  if (idx < 0 || !ctx->timing) return;
+  NQ_HIP(hipEventRecord(ctx->spans[idx].b, ctx->stream));
+}
+
+}  // namespace nq
+
 using namespace nq;
 
 namespace {
@@ -125,9 +160,13 @@ void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int
                     double* energy, double* forces, double* atom_energy) {
   NbrList& nl = ctx->nl;
   const double half = 0.5 * (nl.r_cut + nl.skin - m->dims.rc);
+  int sp = span_begin(ctx, "neighbor_check_rebuild");
   nbr_displacement_check_async(ctx, pos, half);
   nbr_build_async(ctx, pos, true);
+  span_end(ctx, sp);
+  sp = span_begin(ctx, "edge_list");
   edges_build_async(ctx, pos, m->dims.rc);
+  span_end(ctx, sp);
   forward_async(ctx, m, species, n, energy, atom_energy);
   backward_async(ctx, m, n, forces);
 }
@@ -373,6 +412,58 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     NQ_REQUIRE(r * w <= cap, NQ_ERR_CAPACITY, "output too small");
     NQ_HIP(hipMemcpyAsync(out, src, (size_t)r * w * 4, hipMemcpyDeviceToDevice, ctx->stream));
     NQ_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+nq_status nq_timing(nq_ctx* ctx, int enable) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx, NQ_ERR_ARG, "null ctx");
+    ctx->timing = enable != 0;
+  });
+}
+
+nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && len, NQ_ERR_ARG, "null argument");
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    int ne = 0;
+    if (ctx->ws.nedge.p) NQ_HIP(hipMemcpy(&ne, ctx->ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost));
+    struct Agg {
+      int count = 0;
+      double ms = 0, flop = 0, byte = 0;
+    };
+    std::vector<std::string> order;
+    std::vector<Agg> agg;
+    for (const Span& s : ctx->spans) {
+      float ms = 0.f;
+      NQ_HIP(hipEventElapsedTime(&ms, s.a, s.b));
+      size_t k = 0;
+      while (k < order.size() && order[k] != s.name) ++k;
+      if (k == order.size()) {
+        order.push_back(s.name);
+        agg.push_back(Agg());
+      }
+      agg[k].count++;
+      agg[k].ms += ms;
+      agg[k].flop = s.flop_per_edge * ne + s.flop_per_atom * (double)ctx->ws.n_atoms;
+      agg[k].byte = s.byte_per_edge * ne + s.byte_per_atom * (double)ctx->ws.n_atoms;
+      ctx->event_pool.push_back(s.a);
+      ctx->event_pool.push_back(s.b);
+    }
+    ctx->spans.clear();
+    std::string out = "{\"n_edges\": " + std::to_string(ne) + ", \"kernels\": [";
+    char tmp[512];
+    for (size_t k = 0; k < order.size(); ++k) {
+      std::snprintf(tmp, sizeof(tmp),
+                    "%s{\"name\": \"%s\", \"count\": %d, \"ms_total\": %.6f, \"flop_per_launch\": %.6e, "
+                    "\"bytes_per_launch\": %.6e}",
+                    k ? ", " : "", order[k].c_str(), agg[k].count, agg[k].ms, agg[k].flop, agg[k].byte);
+      out += tmp;
+    }
+    out += "]}";
+    *len = (int64_t)out.size();
+    NQ_REQUIRE(buf && cap > (int64_t)out.size(), NQ_ERR_CAPACITY, "report buffer too small");
+    std::memcpy(buf, out.c_str(), out.size() + 1);
   });
 }
 

@@ -27,6 +27,8 @@ __device__ inline float dsiluf(float a) {
 
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 enum ALoadMode { A_PLAIN = 0, A_SILU = 1, A_CAT = 2, A_GRADSILU = 3 };
 
 struct ALoad {
@@ -35,21 +37,33 @@ struct ALoad {
   const float* p1; int ld1; int K1;  // concatenated source, or the pre-activation for A_GRADSILU
   const float* rs; int rs_ld;        // optional per-row scale (the cutoff u)
   float c;                           // constant factor (A_GRADSILU)
-  __device__ inline float operator()(int64_t r, int k) const {
-    switch (mode) {
-      case A_PLAIN: return k < K0 ? p0[r * ld0 + k] : 0.f;
-      case A_SILU: return k < K0 ? siluf(p0[r * ld0 + k]) : 0.f;
-      case A_CAT:
-        if (k < K0) return p0[r * ld0 + k];
-        if (k < K0 + K1) return p1[r * ld1 + (k - K0)];
-        return 0.f;
-      default: {
-        if (k >= K0) return 0.f;
-        float g = p0[r * ld0 + k] * c;
-        if (rs) g *= rs[r * rs_ld];
-        return g * dsiluf(p1[r * ld1 + k]);
+  // Four consecutive columns k..k+3 of row r (k % 4 == 0; widths and leading
+  // dimensions are multiples of 4, so every access is one aligned 16-byte load).
+  __device__ inline float4 load4(int64_t r, int k) const {
+    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+    if (mode == A_CAT) {
+      if (k < K0)
+        v = *reinterpret_cast<const float4*>(p0 + r * ld0 + k);
+      else if (k < K0 + K1)
+        v = *reinterpret_cast<const float4*>(p1 + r * ld1 + (k - K0));
+    } else if (k < K0) {
+      v = *reinterpret_cast<const float4*>(p0 + r * ld0 + k);
+      if (mode == A_SILU) {
+        v.x = siluf(v.x);
+        v.y = siluf(v.y);
+        v.z = siluf(v.z);
+        v.w = siluf(v.w);
+      } else if (mode == A_GRADSILU) {
+        const float4 a = *reinterpret_cast<const float4*>(p1 + r * ld1 + k);
+        float f = c;
+        if (rs) f *= rs[r * rs_ld];
+        v.x *= f * dsiluf(a.x);
+        v.y *= f * dsiluf(a.y);
+        v.z *= f * dsiluf(a.z);
+        v.w *= f * dsiluf(a.w);
       }
     }
+    return v;
   }
 };
 
@@ -103,31 +117,60 @@ __device__ inline void store_tiles(const Epi& ep, const floatx4 (&acc)[MI][NI], 
       }
 }
 
-template <typename T> struct MfmaTraits;
+// Kinds of matrix-core product.
+enum GemmKind { G_F32 = 0, G_BF16 = 1, G_BF16X3 = 2 };
 
-template <> struct MfmaTraits<bf16> {
-  static constexpr int BK = 32;
-  static constexpr int PAD = 8;
+template <int KIND> struct GemmTraits;
+template <> struct GemmTraits<G_F32> {  // A, B: f32 in LDS; v_mfma_f32_16x16x4_f32
+  typedef float AT;
+  typedef float BT;
+  static constexpr int BK = 16, LDA = 20, LDB = 20, BHALVES = 1;
 };
-template <> struct MfmaTraits<float> {
-  static constexpr int BK = 16;
-  static constexpr int PAD = 4;
+template <> struct GemmTraits<G_BF16> {  // A, B: bf16 in LDS; v_mfma_f32_16x16x32_bf16
+  typedef bf16 AT;
+  typedef bf16 BT;
+  static constexpr int BK = 32, LDA = 40, LDB = 40, BHALVES = 1;
 };
+template <> struct GemmTraits<G_BF16X3> {  // A: f32 in LDS split on load; B: bf16 hi and lo
+  typedef float AT;
+  typedef bf16 BT;
+  static constexpr int BK = 32, LDA = 36, LDB = 40, BHALVES = 2;
+};
+
+__device__ inline void split_bf16(const float* v, bf16x8& hi, bf16x8& lo) {
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const bf16 h = (bf16)v[k];
+    hi[k] = h;
+    lo[k] = (bf16)(v[k] - (float)h);
+  }
+}
 
 // C[rows, NP] = A[rows, Kp] * Bt[NP, Kp]^T.  4 wavefronts as WM x WN.
-template <typename T, int BM, int NP, int WM, int WN>
-__global__ __launch_bounds__(256) void k_gemm(int Kp, const T* __restrict__ Bt,
+// For BF16X3, Bt holds two [NP][Kp] halves (hi, lo) and the product is
+// A_hi B_hi + A_lo B_hi + A_hi B_lo. The next K step's A and B tiles are
+// fetched into registers while the matrix cores work on the current one.
+template <int KIND, int BM, int NP, int WM, int WN>
+__global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<KIND>::BT* __restrict__ Bt,
                                               const int* __restrict__ nrows_p, ALoad ld, Epi ep) {
-  constexpr int BK = MfmaTraits<T>::BK;
-  constexpr int LDK = BK + MfmaTraits<T>::PAD;
+  typedef GemmTraits<KIND> Tr;
+  typedef typename Tr::AT AT;
+  typedef typename Tr::BT BT;
+  constexpr int BK = Tr::BK, LDA = Tr::LDA, LDB = Tr::LDB;
   constexpr int RW = BM / WM;  // rows per wave
   constexpr int CW = NP / WN;  // cols per wave
   constexpr int MI = RW / 16;
   constexpr int NI = CW / 16;
+  constexpr int A4 = BM * BK / 4;                      // float4 chunks of one A tile
+  constexpr int NA = (A4 + 255) / 256;                 // ... per thread
+  constexpr int CPR = BK * (int)sizeof(BT) / 16;       // 16-byte chunks per B row
+  constexpr int EPC = 16 / (int)sizeof(BT);            // elements per chunk
+  constexpr int B16 = Tr::BHALVES * NP * CPR;          // chunks of one B tile
+  constexpr int NB = (B16 + 255) / 256;
   static_assert(WM * WN == 4, "4 wavefronts");
   static_assert(RW % 16 == 0 && CW % 16 == 0, "16x16 tiles");
-  __shared__ __attribute__((aligned(16))) T As[BM * LDK];
-  __shared__ __attribute__((aligned(16))) T Bs[NP * LDK];
+  __shared__ __attribute__((aligned(16))) AT As[BM * LDA];
+  __shared__ __attribute__((aligned(16))) BT Bs[Tr::BHALVES * NP * LDB];
 
   const int64_t nrows = *nrows_p;
   const int64_t r0 = (int64_t)blockIdx.x * BM;
@@ -135,6 +178,7 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const T* __restrict__ Bt,
   const int tid = threadIdx.x;
   const int wave = tid / 64, lane = tid % 64;
   const int wm = wave / WN, wn = wave % WN;
+  const int64_t half = (int64_t)NP * Kp;
 
   floatx4 acc[MI][NI];
 #pragma unroll
@@ -142,43 +186,96 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const T* __restrict__ Bt,
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
+  float4 ra[NA];
+  u32x4 rb[NB];
+#define NQ_GEMM_FETCH(K0)                                                                          \
+  {                                                                                               \
+    _Pragma("unroll") for (int q = 0; q < NA; ++q) {                                              \
+      const int idx = tid + 256 * q;                                                              \
+      ra[q] = make_float4(0.f, 0.f, 0.f, 0.f);                                                    \
+      if (idx < A4) {                                                                             \
+        const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;                                 \
+        const int64_t row = r0 + rr;                                                              \
+        if (row < nrows) ra[q] = ld.load4(row, (K0) + kk);                                        \
+      }                                                                                           \
+    }                                                                                             \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) {                                              \
+      const int idx = tid + 256 * q;                                                              \
+      if (idx < B16) {                                                                            \
+        const int h = idx / (NP * CPR), rem = idx % (NP * CPR);                                   \
+        const int n = rem / CPR, ch = rem % CPR;                                                  \
+        rb[q] = *reinterpret_cast<const u32x4*>(Bt + h * half + (int64_t)n * Kp + (K0) + ch * EPC); \
+      }                                                                                           \
+    }                                                                                             \
+  }
+  NQ_GEMM_FETCH(0);
   for (int k0 = 0; k0 < Kp; k0 += BK) {
-    // stage A (BM x BK) through the loader
-    for (int idx = tid; idx < BM * BK; idx += 256) {
-      const int rr = idx / BK, kk = idx % BK;
-      const int64_t row = r0 + rr;
-      float v = (row < nrows) ? ld(row, k0 + kk) : 0.f;
-      As[rr * LDK + kk] = (T)v;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < A4) {
+        const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
+        AT* d = &As[rr * LDA + kk];
+        d[0] = (AT)ra[q].x;
+        d[1] = (AT)ra[q].y;
+        d[2] = (AT)ra[q].z;
+        d[3] = (AT)ra[q].w;
+      }
     }
-    // stage B (NP x BK), 16-byte chunks
-    constexpr int CHUNKS = BK * (int)sizeof(T) / 16;  // 4
-    for (int idx = tid; idx < NP * CHUNKS; idx += 256) {
-      const int n = idx / CHUNKS, ch = idx % CHUNKS;
-      const uint4 v = *reinterpret_cast<const uint4*>(Bt + (int64_t)n * Kp + k0 + ch * (16 / sizeof(T)));
-      *reinterpret_cast<uint4*>(&Bs[n * LDK + ch * (16 / sizeof(T))]) = v;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) {
+      const int idx = tid + 256 * q;
+      if (idx < B16) {
+        const int h = idx / (NP * CPR), rem = idx % (NP * CPR);
+        const int n = rem / CPR, ch = rem % CPR;
+        *reinterpret_cast<u32x4*>(&Bs[(h * NP + n) * LDB + ch * EPC]) = rb[q];
+      }
     }
     __syncthreads();
-    if constexpr (sizeof(T) == 2) {
+    if (k0 + BK < Kp) NQ_GEMM_FETCH(k0 + BK);
+    if constexpr (KIND == G_BF16) {
       bf16x8 a[MI];
 #pragma unroll
       for (int i = 0; i < MI; ++i)
-        a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * RW + i * 16 + lane % 16) * LDK + (lane / 16) * 8]);
+        a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8]);
 #pragma unroll
       for (int j = 0; j < NI; ++j) {
         const bf16x8 b =
-            *reinterpret_cast<const bf16x8*>(&Bs[(wn * CW + j * 16 + lane % 16) * LDK + (lane / 16) * 8]);
+            *reinterpret_cast<const bf16x8*>(&Bs[(wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8]);
 #pragma unroll
         for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+      }
+    } else if constexpr (KIND == G_BF16X3) {
+      bf16x8 ahi[MI], alo[MI];
+#pragma unroll
+      for (int i = 0; i < MI; ++i) {
+        const float* src = &As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8];
+        float v[8];
+        *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(src);
+        *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(src + 4);
+        split_bf16(v, ahi[i], alo[i]);
+      }
+#pragma unroll
+      for (int j = 0; j < NI; ++j) {
+        const int nb = (wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8;
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&Bs[nb]);
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&Bs[NP * LDB + nb]);
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo, acc[i][j], 0, 0, 0);
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi, acc[i][j], 0, 0, 0);
+        }
       }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
         float a[MI];
 #pragma unroll
-        for (int i = 0; i < MI; ++i) a[i] = As[(wm * RW + i * 16 + lane % 16) * LDK + kk + lane / 16];
+        for (int i = 0; i < MI; ++i) a[i] = As[(wm * RW + i * 16 + lane % 16) * LDA + kk + lane / 16];
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
-          const float b = Bs[(wn * CW + j * 16 + lane % 16) * LDK + kk + lane / 16];
+          const float b = Bs[(wn * CW + j * 16 + lane % 16) * LDB + kk + lane / 16];
 #pragma unroll
           for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
         }
@@ -186,14 +283,15 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const T* __restrict__ Bt,
     }
     __syncthreads();
   }
-  const int64_t rb = r0 + wm * RW;
-  const int cb = wn * CW;
+#undef NQ_GEMM_FETCH
+  const int64_t rbase = r0 + wm * RW;
+  const int cbase = wn * CW;
   switch (ep.mode) {
-    case E_STORE: store_tiles<E_STORE>(ep, acc, rb, cb, lane, nrows); break;
-    case E_STORE_X0: store_tiles<E_STORE_X0>(ep, acc, rb, cb, lane, nrows); break;
-    case E_RESIDUAL: store_tiles<E_RESIDUAL>(ep, acc, rb, cb, lane, nrows); break;
-    case E_LATENT_BWD: store_tiles<E_LATENT_BWD>(ep, acc, rb, cb, lane, nrows); break;
-    default: store_tiles<E_ADD>(ep, acc, rb, cb, lane, nrows); break;
+    case E_STORE: store_tiles<E_STORE>(ep, acc, rbase, cbase, lane, nrows); break;
+    case E_STORE_X0: store_tiles<E_STORE_X0>(ep, acc, rbase, cbase, lane, nrows); break;
+    case E_RESIDUAL: store_tiles<E_RESIDUAL>(ep, acc, rbase, cbase, lane, nrows); break;
+    case E_LATENT_BWD: store_tiles<E_LATENT_BWD>(ep, acc, rbase, cbase, lane, nrows); break;
+    default: store_tiles<E_ADD>(ep, acc, rbase, cbase, lane, nrows); break;
   }
 }
 

@@ -35,8 +35,9 @@ Dims make_dims(const nq_model_desc& d) {
   NQ_REQUIRE(d.n_latent >= 1 && d.n_latent <= 4, NQ_ERR_UNSUPPORTED, "1..4 latent layers");
   NQ_REQUIRE(d.n_edge >= 1 && d.n_edge <= 4, NQ_ERR_UNSUPPORTED, "1..4 hidden edge layers");
   NQ_REQUIRE(d.r_cut > 0 && d.avg_num_neighbors > 0, NQ_ERR_ARG, "r_cut and nu must be > 0");
-  NQ_REQUIRE(d.precision == NQ_PRECISION_FP32 || d.precision == NQ_PRECISION_BF16, NQ_ERR_ARG,
-             "unknown precision");
+  NQ_REQUIRE(d.precision == NQ_PRECISION_FP32 || d.precision == NQ_PRECISION_BF16 ||
+                 d.precision == NQ_PRECISION_BF16X3,
+             NQ_ERR_ARG, "unknown precision");
   m.S = d.n_species;
   m.nb = d.n_bessel;
   m.p = d.poly_p;
@@ -205,6 +206,14 @@ uint16_t bf16_bits_rne(double d) {
   return (uint16_t)(r >> 16);
 }
 
+double bf16_value(uint16_t b) {
+  uint32_t u = (uint32_t)b << 16;
+  float f;
+  std::memcpy(&f, &u, 4);
+  return (double)f;
+}
+
+// BF16 copies are stored as [hi | lo] halves: hi = rne(w), lo = rne(w - hi).
 void upload_lin(Lin& L, const double* W, int fin, int fout) {
   L.fin = fin;
   L.fout = fout;
@@ -213,14 +222,19 @@ void upload_lin(Lin& L, const double* W, int fin, int fout) {
   L.kp_b = (int)rup(fout, 32);
   L.np_b = (int)rup(fin, 16);
   std::vector<float> ff((size_t)L.np_f * L.kp_f, 0.f), fb((size_t)L.np_b * L.kp_b, 0.f);
-  std::vector<uint16_t> bf((size_t)L.np_f * L.kp_f, 0), bb((size_t)L.np_b * L.kp_b, 0);
+  const size_t hf = (size_t)L.np_f * L.kp_f, hb = (size_t)L.np_b * L.kp_b;
+  std::vector<uint16_t> bf(2 * hf, 0), bb(2 * hb, 0);
   for (int k = 0; k < fin; ++k)
     for (int n = 0; n < fout; ++n) {
-      double w = W[(size_t)k * fout + n];
+      const double w = W[(size_t)k * fout + n];
+      const uint16_t hi = bf16_bits_rne(w);
+      const uint16_t lo = bf16_bits_rne(w - bf16_value(hi));
       ff[(size_t)n * L.kp_f + k] = (float)w;
-      bf[(size_t)n * L.kp_f + k] = bf16_bits_rne(w);
+      bf[(size_t)n * L.kp_f + k] = hi;
+      bf[hf + (size_t)n * L.kp_f + k] = lo;
       fb[(size_t)k * L.kp_b + n] = (float)w;
-      bb[(size_t)k * L.kp_b + n] = bf16_bits_rne(w);
+      bb[(size_t)k * L.kp_b + n] = hi;
+      bb[hb + (size_t)k * L.kp_b + n] = lo;
     }
   L.f32_fwd.ensure(ff.size() * 4);
   L.f32_bwd.ensure(fb.size() * 4);

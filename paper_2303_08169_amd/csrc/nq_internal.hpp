@@ -82,6 +82,7 @@ struct Dims {
 //       padded to 32, Np = fout padded to 16.
 //  bwd: B operand of gx = gy W^T, laid out [Np][Kp] = W with fin padded to 16 rows
 //       and fout padded to 32 columns.
+//  The BF16 buffers hold two [Np][Kp] halves: hi = rne(w) and lo = rne(w - hi).
 struct Lin {
   int fin = 0, fout = 0;
   int kp_f = 0, np_f = 0, kp_b = 0, np_b = 0;
@@ -147,6 +148,16 @@ struct Workspace {
 
 }  // namespace nq
 
+namespace nq {
+// One timed launch (or group of launches) recorded while timing is enabled.
+struct Span {
+  std::string name;
+  hipEvent_t a = nullptr, b = nullptr;
+  double flop_per_edge = 0, byte_per_edge = 0;  // algorithmic work per in-cutoff edge
+  double flop_per_atom = 0, byte_per_atom = 0;  // ... or per atom
+};
+}  // namespace nq
+
 struct nq_ctx {
   int device = 0;
   hipStream_t stream = nullptr;
@@ -160,6 +171,10 @@ struct nq_ctx {
   std::vector<const void*> graph_key;
   nq::DevBuf md_scratch;
   int64_t last_edges = 0;
+  // per-launch timing with HIP events on the context's stream
+  bool timing = false;
+  std::vector<nq::Span> spans;
+  std::vector<hipEvent_t> event_pool;
 };
 
 namespace nq {
@@ -189,6 +204,11 @@ void md_drift_async(hipStream_t s, double* pos, const double* vel, int64_t n, do
                     const double box[3]);
 void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n,
                    double* out);
+
+// Start/stop a timed span on ctx->stream (no-ops unless timing is enabled).
+int span_begin(nq_ctx* ctx, const std::string& name, double flop_per_edge = 0, double byte_per_edge = 0,
+               double flop_per_atom = 0, double byte_per_atom = 0);
+void span_end(nq_ctx* ctx, int idx);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 inline int64_t rup(int64_t a, int64_t b) { return cdiv(a, b) * b; }

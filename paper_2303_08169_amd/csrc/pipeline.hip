@@ -51,20 +51,22 @@ __device__ inline void sph(float x, float y, float z, float* Y) {
   Y[8] = 0.5f * s15 * (x * x - y * y);
 }
 
-// Polynomial cutoff u(x) and du/dx, x = d / r_c.
+// Polynomial cutoff u(x) and du/dx, x = d / r_c. The polynomial
+// 1 - (p+1)(p+2)/2 x^p + p(p+2) x^(p+1) - p(p+1)/2 x^(p+2) has a triple root at
+// x = 1 and equals (1-x)^3 * sum_{k<p} (k+1)(k+2)/2 x^k; that factored form
+// keeps full relative accuracy near the cutoff, where the expanded one cancels.
 __device__ inline void envelope(float x, int p, float& u, float& du) {
   if (x >= 1.f) {
     u = 0.f;
     du = 0.f;
     return;
   }
-  float xp1 = 1.f;  // x^(p-1)
+  float q = 0.f, xp1 = 1.f;  // xp1 = x^(p-1)
+  for (int k = p - 1; k >= 0; --k) q = q * x + 0.5f * (float)((k + 1) * (k + 2));
   for (int k = 0; k < p - 1; ++k) xp1 *= x;
-  const float xp = xp1 * x;
-  const float c0 = 0.5f * (p + 1) * (p + 2), c1 = (float)(p * (p + 2)), c2 = 0.5f * p * (p + 1);
-  u = 1.f - c0 * xp + c1 * xp * x - c2 * xp * x * x;
   const float om = 1.f - x;
-  du = -0.5f * p * (p + 1) * (p + 2) * xp1 * om * om;
+  u = om * om * om * q;
+  du = -0.5f * (float)(p * (p + 1) * (p + 2)) * xp1 * om * om;
 }
 
 // ------------------------------------------------------------------ geometry
@@ -547,44 +549,72 @@ __global__ void k_forces(int64_t n, const int* __restrict__ nedge_p, const int* 
 }
 
 // ------------------------------------------------------------------ GEMM dispatch
-template <typename T, int BM, int NP, int WM, int WN>
-void launch_gemm_t(hipStream_t s, int64_t cap, int Kp, const T* Bt, const int* nrows, const ALoad& ld,
+template <int KIND, int BM, int NP, int WM, int WN>
+void launch_gemm_t(hipStream_t s, int64_t cap, int Kp, const void* Bt, const int* nrows, const ALoad& ld,
                    const Epi& ep) {
-  k_gemm<T, BM, NP, WM, WN><<<(unsigned)cdiv(cap, BM), 256, 0, s>>>(Kp, Bt, nrows, ld, ep);
+  typedef typename GemmTraits<KIND>::BT BT;
+  k_gemm<KIND, BM, NP, WM, WN><<<(unsigned)cdiv(cap, BM), 256, 0, s>>>(Kp, static_cast<const BT*>(Bt), nrows, ld,
+                                                                       ep);
 }
 
-template <typename T>
-void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const T* Bt, const int* nrows, const ALoad& ld,
+// Tile shapes per output width; the split-BF16 kind keeps both weight halves
+// in LDS, so its wide shapes use fewer rows per workgroup.
+template <int KIND>
+void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, const int* nrows, const ALoad& ld,
                     const Epi& ep) {
+  constexpr bool X3 = KIND == G_BF16X3;
   switch (NP) {
-    case 16: launch_gemm_t<T, 128, 16, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 32: launch_gemm_t<T, 128, 32, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 48: launch_gemm_t<T, 128, 48, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 64: launch_gemm_t<T, 128, 64, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 96: launch_gemm_t<T, 128, 96, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 128: launch_gemm_t<T, 128, 128, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 192: launch_gemm_t<T, 128, 192, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 256: launch_gemm_t<T, 128, 256, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 352: launch_gemm_t<T, 64, 352, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 384: launch_gemm_t<T, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 512: launch_gemm_t<T, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 704: launch_gemm_t<T, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 16: launch_gemm_t<KIND, 128, 16, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 32: launch_gemm_t<KIND, 128, 32, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 48: launch_gemm_t<KIND, 128, 48, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 64: launch_gemm_t<KIND, 128, 64, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 96: launch_gemm_t<KIND, 128, 96, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 128: launch_gemm_t<KIND, 128, 128, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 192: launch_gemm_t<KIND, 64, 192, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 256: launch_gemm_t<KIND, 64, 256, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 352: launch_gemm_t<KIND, X3 ? 32 : 64, 352, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
+    case 384:
+      if constexpr (!X3) {
+        launch_gemm_t<KIND, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+        break;
+      }
+      [[fallthrough]];
+    case 512:
+      if constexpr (!X3) {
+        launch_gemm_t<KIND, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+        break;
+      }
+      [[fallthrough]];
+    case 704:
+      if constexpr (!X3) {
+        launch_gemm_t<KIND, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep);
+        break;
+      }
+      [[fallthrough]];
     default: throw Error{NQ_ERR_UNSUPPORTED, "no matrix-core kernel for output width " + std::to_string(NP)};
   }
 }
 
 // y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map.
-void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep) {
+void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep,
+          const std::string& name) {
   const Workspace& ws = ctx->ws;
+  const int sp = span_begin(ctx, name, 2.0 * L.fin * L.fout, 4.0 * (L.fin + L.fout));
   const int NP = bwd ? L.np_b : L.np_f;
   const int Kp = bwd ? L.kp_b : L.kp_f;
-  if (m->dims.prec == NQ_PRECISION_BF16)
-    launch_gemm_np<bf16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).as<bf16>(), ws.nedge.as<int>(),
-                         ld, ep);
-  else
-    launch_gemm_np<float>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).as<float>(),
-                          ws.nedge.as<int>(), ld, ep);
+  const int* nr = ws.nedge.as<int>();
+  switch (m->dims.prec) {
+    case NQ_PRECISION_BF16:
+      launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep);
+      break;
+    case NQ_PRECISION_BF16X3:
+      launch_gemm_np<G_BF16X3>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep);
+      break;
+    default:
+      launch_gemm_np<G_F32>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).p, nr, ld, ep);
+  }
   NQ_HIP(hipGetLastError());
+  span_end(ctx, sp);
 }
 
 ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
@@ -683,13 +713,17 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64
   const int* ne = ws.nedge.as<int>();
   const int64_t cap = ws.cap;
   const float* u = ws.geo + 1;
-  k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.rij.as<float4>(), ws.ei.as<int>(), ws.ej.as<int>(),
-                                                      species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
-                                                 ctx->nl.flags.as<int>());
+  {
+    const int sp_ = span_begin(ctx, "geometry");
+    k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.rij.as<float4>(), ws.ei.as<int>(), ws.ej.as<int>(),
+                                                        species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
+                                                   ctx->nl.flags.as<int>());
+    span_end(ctx, sp_);
+  }
   // two-body MLP; the last layer stores x0 = u * SiLU(a)
   for (int k = 0; k < d.n_tb; ++k) {
     const Lin& L = *m->tb[k];
-    ALoad ld = k == 0 ? a_plain(ws.h0, ws.K0p, d.n_in2b) : a_silu(ws.a_tb[k - 1], d.tb[k - 1], d.tb[k - 1]);
+    ALoad ld = k == 0 ? a_plain(ws.h0, ws.K0p, ws.K0p) : a_silu(ws.a_tb[k - 1], d.tb[k - 1], d.tb[k - 1]);
     Epi ep = e_store(ws.a_tb[k], d.tb[k], d.tb[k]);
     if (k == d.n_tb - 1) {
       ep.mode = E_STORE_X0;
@@ -698,31 +732,49 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64
       ep.rs = u;
       ep.rs_ld = kGeo;
     }
-    gemm(ctx, m, L, false, ld, ep);
+    gemm(ctx, m, L, false, ld, ep, "fwd.twobody." + std::to_string(k));
   }
-  gemm(ctx, m, m->v0e1, false, a_plain(ws.x[0], d.D, d.D), e_store(ws.we1, 2 * d.NW, 2 * d.NW));
+  gemm(ctx, m, m->v0e1, false, a_plain(ws.x[0], d.D, d.D), e_store(ws.we1, 2 * d.NW, 2 * d.NW), "fwd.v0env1");
   const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
   for (int t = 1; t <= d.T; ++t) {
     const bool last = t == d.T;
-    if (t > 1) gemm(ctx, m, *m->env[t - 1], false, a_plain(ws.x[t - 1], d.D, d.D), e_store(ws.e[t], d.NW, d.NW));
+    if (t > 1)
+      gemm(ctx, m, *m->env[t - 1], false, a_plain(ws.x[t - 1], d.D, d.D), e_store(ws.e[t], d.NW, d.NW),
+           "fwd.env" + std::to_string(t));
     const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
     const int lde = t == 1 ? 2 * d.NW : d.NW;
     if (d.L == 1)
-      k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
-                                                        ws.gam[t]);
+      {
+        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
+        k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+                                                          ws.gam[t]);
+        span_end(ctx, sp_);
+      }
     else
-      k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
-                                                        ws.gam[t]);
+      {
+        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
+        k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+                                                          ws.gam[t]);
+        span_end(ctx, sp_);
+      }
     const int epb = 256 / d.C;
     const float* mix = last ? nullptr : m->mix.as<float>() + m->mix_off[t - 1];
     if (d.L == 1)
-      k_tp_fwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
-                                                           ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+      {
+        const int sp_ = span_begin(ctx, "tp_fwd" + std::to_string(t));
+        k_tp_fwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
+                                                             ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+        span_end(ctx, sp_);
+      }
     else
-      k_tp_fwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
-                                                           ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+      {
+        const int sp_ = span_begin(ctx, "tp_fwd" + std::to_string(t));
+        k_tp_fwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
+                                                             ws.s[t], d.nscal * d.C, mix, ws.V[t]);
+        span_end(ctx, sp_);
+      }
     NQ_HIP(hipGetLastError());
     // latent MLP on [x | s]; the last layer applies the residual update
     for (int k = 0; k < d.n_lat; ++k) {
@@ -739,18 +791,30 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64
         ep.rs = u;
         ep.rs_ld = kGeo;
       }
-      gemm(ctx, m, L, false, ld, ep);
+      gemm(ctx, m, L, false, ld, ep, "fwd.latent" + std::to_string(t) + "." + std::to_string(k));
     }
   }
   for (int k = 0; k < d.n_edge; ++k) {
     ALoad ld = k == 0 ? a_plain(ws.x[d.T], d.D, d.D) : a_silu(ws.a_edge[k - 1], d.edge[k - 1], d.edge[k - 1]);
-    gemm(ctx, m, *m->edge[k], false, ld, e_store(ws.a_edge[k], d.edge[k], d.edge[k]));
+    gemm(ctx, m, *m->edge[k], false, ld, e_store(ws.a_edge[k], d.edge[k], d.edge[k]), "fwd.edge." + std::to_string(k));
   }
   const int ke = d.n_edge - 1;
-  k_edge_energy<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.a_edge[ke], d.edge[ke], d.edge[ke],
-                                                        m->wout.as<float>(), (float)d.sigma_e, ws.eij);
-  k_atom_energy<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.eij, ws.atomE, atom_energy);
-  k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+  {
+    const int sp_ = span_begin(ctx, "edge_energy");
+    k_edge_energy<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.a_edge[ke], d.edge[ke], d.edge[ke],
+                                                          m->wout.as<float>(), (float)d.sigma_e, ws.eij);
+    span_end(ctx, sp_);
+  }
+  {
+    const int sp_ = span_begin(ctx, "atom_energy");
+    k_atom_energy<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.eij, ws.atomE, atom_energy);
+    span_end(ctx, sp_);
+  }
+  {
+    const int sp_ = span_begin(ctx, "total_energy");
+    k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+    span_end(ctx, sp_);
+  }
   NQ_HIP(hipGetLastError());
 }
 
@@ -762,8 +826,16 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
   const int* ne = ws.nedge.as<int>();
   const int64_t cap = ws.cap;
   const float* u = ws.geo + 1;
-  k_fill<<<grid_for(cap, 256), 256, 0, s>>>(ws.gu, cap, 0.f);
-  k_fill<<<grid_for(cap * 16, 256), 256, 0, s>>>(ws.gY, cap * 16, 0.f);
+  {
+    const int sp_ = span_begin(ctx, "fill");
+    k_fill<<<grid_for(cap, 256), 256, 0, s>>>(ws.gu, cap, 0.f);
+    span_end(ctx, sp_);
+  }
+  {
+    const int sp_ = span_begin(ctx, "fill");
+    k_fill<<<grid_for(cap * 16, 256), 256, 0, s>>>(ws.gY, cap * 16, 0.f);
+    span_end(ctx, sp_);
+  }
   // edge MLP: g_a(last) = sigma_E w_out SiLU'(a)
   {
     float* gout = nullptr;
@@ -774,7 +846,7 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
                      : a_gradsilu(gout, ws.maxw, d.edge[k], ws.a_edge[k], d.edge[k], nullptr, 1.f);
       const int fin = k == 0 ? d.D : d.edge[k - 1];
       float* dst = k == 0 ? ws.gx : ws.gh[k % 2];
-      gemm(ctx, m, *m->edge[k], true, ld, e_store(dst, k == 0 ? d.D : ws.maxw, fin));
+      gemm(ctx, m, *m->edge[k], true, ld, e_store(dst, k == 0 ? d.D : ws.maxw, fin), "bwd.edge." + std::to_string(k));
       gout = dst;
     }
   }
@@ -783,8 +855,12 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
   for (int t = d.T; t >= 1; --t) {
     const bool last = t == d.T;
     const int kl = d.n_lat - 1;
-    k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_lat[t][kl], d.lat[kl], d.D, kInvSqrt2,
-                                                        ws.gu);
+    {
+      const int sp_ = span_begin(ctx, "rowdot_gu" + std::to_string(t));
+      k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_lat[t][kl], d.lat[kl], d.D, kInvSqrt2,
+                                                          ws.gu);
+      span_end(ctx, sp_);
+    }
     float* gout = nullptr;
     for (int k = kl; k >= 0; --k) {
       ALoad ld = k == kl ? a_gradsilu(ws.gx, d.D, d.lat[k], ws.a_lat[t][k], d.lat[k], u, kInvSqrt2)
@@ -795,7 +871,7 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
       } else {
         ep = e_store(ws.gh[k % 2], ws.maxw, d.lat[k - 1]);
       }
-      gemm(ctx, m, *m->lat[t - 1][k], true, ld, ep);
+      gemm(ctx, m, *m->lat[t - 1][k], true, ld, ep, "bwd.latent" + std::to_string(t) + "." + std::to_string(k));
       gout = ws.gh[k % 2];
     }
     // tensor-product adjoint
@@ -804,45 +880,74 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
     const float* gvin = last ? nullptr : ws.gv[gvcur];
     float* gvout = ws.gv[1 - gvcur];
     if (d.L == 1)
-      k_tp_bwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
-                                                           d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
-                                                           ws.gY);
+      {
+        const int sp_ = span_begin(ctx, "tp_bwd" + std::to_string(t));
+        k_tp_bwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
+                                                             d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
+                                                             ws.gY);
+        span_end(ctx, sp_);
+      }
     else
-      k_tp_bwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                           2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
-                                                           d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
-                                                           ws.gY);
+      {
+        const int sp_ = span_begin(ctx, "tp_bwd" + std::to_string(t));
+        k_tp_bwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
+                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
+                                                             d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
+                                                             ws.gY);
+        span_end(ctx, sp_);
+      }
     gvcur = 1 - gvcur;
     // environment-sum adjoint -> gew[:, NW:2NW], gY
     const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
     const int lde = t == 1 ? 2 * d.NW : d.NW;
     if (d.L == 1)
-      k_env_bwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
-                                                        inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+      {
+        const int sp_ = span_begin(ctx, "env_bwd" + std::to_string(t));
+        k_env_bwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
+                                                          inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+        span_end(ctx, sp_);
+      }
     else
-      k_env_bwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
-                                                        inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+      {
+        const int sp_ = span_begin(ctx, "env_bwd" + std::to_string(t));
+        k_env_bwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
+                                                          inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
+        span_end(ctx, sp_);
+      }
     NQ_HIP(hipGetLastError());
     if (t > 1)
-      gemm(ctx, m, *m->env[t - 1], true, a_plain(ws.gew + d.NW, 2 * d.NW, d.NW), e_add(ws.gx, d.D, d.D));
+      gemm(ctx, m, *m->env[t - 1], true, a_plain(ws.gew + d.NW, 2 * d.NW, d.NW), e_add(ws.gx, d.D, d.D),
+           "bwd.env" + std::to_string(t));
     else
-      gemm(ctx, m, m->v0e1, true, a_plain(ws.gew, 2 * d.NW, 2 * d.NW), e_add(ws.gx, d.D, d.D));
+      gemm(ctx, m, m->v0e1, true, a_plain(ws.gew, 2 * d.NW, 2 * d.NW), e_add(ws.gx, d.D, d.D), "bwd.v0env1");
   }
   // two-body MLP: x0 = u SiLU(a_last)
   const int kt = d.n_tb - 1;
-  k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_tb[kt], d.tb[kt], d.D, 1.f, ws.gu);
+  {
+    const int sp_ = span_begin(ctx, "rowdot_gu");
+    k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_tb[kt], d.tb[kt], d.D, 1.f, ws.gu);
+    span_end(ctx, sp_);
+  }
   float* gout = nullptr;
   for (int k = kt; k >= 0; --k) {
     ALoad ld = k == kt ? a_gradsilu(ws.gx, d.D, d.tb[k], ws.a_tb[k], d.tb[k], u, 1.f)
                        : a_gradsilu(gout, ws.maxw, d.tb[k], ws.a_tb[k], d.tb[k], nullptr, 1.f);
     const int fin = k == 0 ? d.n_in2b : d.tb[k - 1];
-    gemm(ctx, m, *m->tb[k], true, ld, e_store(ws.gh[k % 2], ws.maxw, fin));
+    gemm(ctx, m, *m->tb[k], true, ld, e_store(ws.gh[k % 2], ws.maxw, fin), "bwd.twobody." + std::to_string(k));
     gout = ws.gh[k % 2];
   }
-  k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
-                                                          d.p, (float)d.rc, d.NY, ws.gr);
-  k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr, forces);
+  {
+    const int sp_ = span_begin(ctx, "geometry_bwd");
+    k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
+                                                            d.p, (float)d.rc, d.NY, ws.gr);
+    span_end(ctx, sp_);
+  }
+  {
+    const int sp_ = span_begin(ctx, "forces");
+    k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr, forces);
+    span_end(ctx, sp_);
+  }
   NQ_HIP(hipGetLastError());
 }
 

@@ -1,0 +1,212 @@
+"""GPU parity of the HIP path against the FP64 oracle, through the C ABI.
+
+Edge lists are compared exactly (integer work). Energies and forces are
+compared element by element with the tolerances of tests/gpu_common.py, on the
+64-atom and 1,024-atom systems (the latter spans many GEMM tiles and has a
+ragged last tile) and, at the full 27,648-atom size in the launch
+configuration the benchmark times, on sampled atoms whose oracle forces are
+exact (all centres within the cutoff of the atom are evaluated).
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from tests.gpu_common import TOL, checksum, golden, rel_rms, system
+
+pytestmark = pytest.mark.gpu
+
+
+def _potential(cf, w, prec):
+    from paper_2303_08169_amd.potential import Potential
+    return Potential(cf.model, w, prec)
+
+
+def _dev(pos, z):
+    return (torch.tensor(pos, device="cuda"), torch.tensor(np.asarray(z), dtype=torch.int32, device="cuda"))
+
+
+@pytest.mark.parametrize("name", ["nh3_64_l1", "nh3_1024_l2"])
+def test_edge_list_is_exact(name):
+    cf, pos, z, L, w = system(name)
+    pot = _potential(cf, w, "fp32")
+    P, Z = _dev(pos, z)
+    pot.energy_forces(P, Z, L)
+    ei, ej = pot.edges()
+    oi, oj = oracle.edge_list(pos, L, cf.model.r_cut)
+    np.testing.assert_array_equal(ei.cpu().numpy(), oi)
+    np.testing.assert_array_equal(ej.cpu().numpy(), oj)
+    pot.close()
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_edge_list_random_boxes(seed):
+    """Atoms crowded against faces and corners, box sizes with 1, 2 and 3+ cells per axis."""
+    cf, _, _, _, w = system("nh3_64_l1")
+    rng = np.random.default_rng(seed)
+    L = [8.9, 9.5, 12.5, 17.0][seed]
+    n = int(rng.integers(40, 300))
+    pos = rng.uniform(0, L, size=(n, 3))
+    k = n // 3
+    pos[:k] = np.mod(rng.choice([0.0, L - 1e-7], size=(k, 3)) + rng.uniform(-0.4, 0.4, size=(k, 3)), L)
+    # keep atoms at least 0.5 A apart
+    keep = [0]
+    for a in range(1, n):
+        d = pos[keep] - pos[a]
+        d -= L * np.round(d / L)
+        if np.min(np.linalg.norm(d, axis=1)) > 0.5:
+            keep.append(a)
+    pos = pos[keep]
+    z = rng.integers(0, 3, size=len(pos)).astype(np.int32)
+    pot = _potential(cf, w, "fp32")
+    P, Z = _dev(pos, z)
+    E, F = pot.energy_forces(P, Z, L)
+    ei, ej = pot.edges()
+    oi, oj = oracle.edge_list(pos, L, cf.model.r_cut)
+    np.testing.assert_array_equal(ei.cpu().numpy(), oi)
+    np.testing.assert_array_equal(ej.cpu().numpy(), oj)
+    E0, F0 = oracle.energy_forces(pos, z, L, cf.model, w)
+    assert abs(E.item() - E0) <= TOL["fp32"]["energy"] * abs(E0)
+    assert rel_rms(F.cpu().numpy(), F0) <= TOL["fp32"]["force"]
+    pot.close()
+
+
+def test_stages_match_oracle_small():
+    """Per-stage intermediates of the FP32 path on the 64-atom system."""
+    cf, pos, z, L, w = system("nh3_64_l1")
+    tr = {}
+    oracle.energy_forces(pos, z, L, cf.model, w, trace=tr)
+    pot = _potential(cf, w, "fp32")
+    P, Z = _dev(pos, z)
+    pot.energy_forces(P, Z, L)
+    torch.cuda.synchronize()
+    nE = len(tr["ei"])
+    geo = pot.debug("geom", 1 << 24).cpu().numpy()
+    assert geo.shape[0] == nE
+    np.testing.assert_allclose(geo[:, 0], tr["d"], rtol=1e-6)
+    np.testing.assert_allclose(geo[:, 1], tr["u"], atol=1e-6)
+    np.testing.assert_allclose(geo[:, 5:5 + tr["Y"].shape[1]], tr["Y"], atol=2e-6)
+    for key in ["x0", "s1", "x1"]:
+        g = pot.debug(key, 1 << 24).cpu().numpy()
+        assert rel_rms(g, tr[key].reshape(nE, -1)) < 1e-5, key
+    eij = pot.debug("eij", 1 << 24).cpu().numpy()[:, 0]
+    assert rel_rms(eij, tr["Eij"]) < 1e-5
+    # Gamma: GPU layout [centre][lm][c], oracle per-l blocks [c][m]
+    C, Lm = cf.model.channels, cf.model.lmax
+    gam = pot.debug("gamma1", 1 << 24).cpu().numpy().reshape(len(pos), (Lm + 1) ** 2, C)
+    blocks = [gam[:, l * l:(l + 1) ** 2, :].transpose(0, 2, 1).reshape(len(pos), -1) for l in range(Lm + 1)]
+    assert rel_rms(np.concatenate(blocks, axis=1), tr["gamma1"]) < 1e-5
+    g = pot.debug("g", 1 << 24).cpu().numpy()[:, :3]
+    assert rel_rms(g, tr["g"]) < 1e-5
+    pot.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
+def test_energy_forces_small(prec):
+    cf, pos, z, L, w = system("nh3_64_l1")
+    g = golden("nh3_64_l1")
+    assert abs(checksum(pos) - g["pos_checksum"]) < 1e-9 * abs(g["pos_checksum"])
+    pot = _potential(cf, w, prec)
+    P, Z = _dev(pos, z)
+    E, F, Ei = pot.energy_forces(P, Z, L, atom_energy=True)
+    torch.cuda.synchronize()
+    assert abs(E.item() - g["energy"]) <= TOL[prec]["energy"] * abs(g["energy"])
+    assert rel_rms(F.cpu().numpy(), g["forces"]) <= TOL[prec]["force"]
+    assert rel_rms(Ei.cpu().numpy(), g["atom_energy"]) <= 10 * TOL[prec]["energy"]
+    pot.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_energy_forces_1024(prec):
+    cf, pos, z, L, w = system("nh3_1024_l2")
+    g = golden("nh3_1024_l2")
+    assert abs(checksum(pos) - g["pos_checksum"]) < 1e-9 * abs(g["pos_checksum"])
+    pot = _potential(cf, w, prec)
+    P, Z = _dev(pos, z)
+    E, F, Ei = pot.energy_forces(P, Z, L, atom_energy=True)
+    torch.cuda.synchronize()
+    F = F.cpu().numpy()
+    assert abs(E.item() - g["energy"]) <= TOL[prec]["energy"] * abs(g["energy"])
+    assert rel_rms(F, g["forces"]) <= TOL[prec]["force"]
+    assert rel_rms(Ei.cpu().numpy(), g["atom_energy"]) <= 10 * TOL[prec]["energy"]
+    # central finite differences (h = 1e-4 A) of the oracle energy on 32 atoms
+    fd = g["fd_forces"]
+    got = F[g["fd_atoms"]]
+    scale = np.abs(fd).max()
+    assert np.abs(got - fd).max() <= max(TOL[prec]["force"], 1e-6) * 10 * scale
+    np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-5 * np.abs(F).sum())
+    pot.close()
+
+
+def test_full_size_sampled_bf16x3():
+    """27,648 atoms in the benchmark's configuration: exact oracle forces on
+    sampled atoms, per-centre energies, and zero net force."""
+    cf, pos, z, L, w = system("nh3_27648_l2")
+    pot = _potential(cf, w, "bf16x3")
+    P, Z = _dev(pos, z)
+    E, F, Ei = pot.energy_forces(P, Z, L, atom_energy=True)
+    torch.cuda.synchronize()
+    ne, _ = pot.stats()
+    F, Ei = F.cpu().numpy(), Ei.cpu().numpy()
+    rng = np.random.default_rng(7)
+    atoms = rng.choice(len(pos), 3, replace=False)
+    cs = [atoms] + [oracle.edge_list(pos, L, cf.model.r_cut, centers=[a])[1] for a in atoms]
+    centers = np.unique(np.concatenate(cs))
+    _, F0, E0 = oracle.energy_forces(pos, z, L, cf.model, w, centers=centers, atom_energy=True)
+    assert rel_rms(F[atoms], F0[atoms]) <= TOL["bf16x3"]["force"]
+    assert rel_rms(Ei[centers], E0[centers]) <= 10 * TOL["bf16x3"]["energy"]
+    assert abs(E.item() - Ei.sum()) <= 1e-9 * np.abs(Ei).sum()
+    np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-6 * np.abs(F).sum())
+    assert abs(ne / len(pos) - cf.model.avg_num_neighbors) < 0.05 * cf.model.avg_num_neighbors
+    pot.close()
+
+
+def test_invariances_on_gpu():
+    cf, pos, z, L, w = system("nh3_1024_l2")
+    pot = _potential(cf, w, "fp32")
+    E0, F0 = pot.energy_forces(*_dev(pos, z), L)
+    E0, F0 = E0.item(), F0.cpu().numpy()
+    shift = np.array([3.3, -1.7, 10.1])
+    E1, F1 = pot.energy_forces(*_dev(np.mod(pos + shift, L), z), L)
+    assert abs(E1.item() - E0) < 1e-5 * abs(E0)
+    assert rel_rms(F1.cpu().numpy(), F0) < 1e-5
+    perm = np.random.default_rng(3).permutation(len(pos))
+    E2, F2 = pot.energy_forces(*_dev(pos[perm], z[perm]), L)
+    assert abs(E2.item() - E0) < 1e-5 * abs(E0)
+    assert rel_rms(F2.cpu().numpy(), F0[perm]) < 1e-5
+    E3, F3 = pot.energy_forces(*_dev(np.mod(-pos, L), z), L)
+    assert abs(E3.item() - E0) < 1e-5 * abs(E0)
+    assert rel_rms(F3.cpu().numpy(), -F0) < 1e-5
+    pot.close()
+
+
+def test_degenerate_systems():
+    cf, _, _, _, w = system("nh3_64_l1")
+    pot = _potential(cf, w, "fp32")
+    L = 20.0
+    # atoms farther apart than the cutoff: no edges, E = 0, F = 0
+    far = np.array([[1.0, 1.0, 1.0], [9.0, 9.0, 9.0], [1.0, 9.0, 15.0]])
+    E, F = pot.energy_forces(*_dev(far, [0, 1, 2]), L)
+    assert E.item() == 0.0 and np.all(F.cpu().numpy() == 0.0)
+    assert pot.stats()[0] == 0
+    # a dimer and an isolated atom
+    pos = np.array([[5.0, 5.0, 5.0], [6.3, 5.4, 4.8], [15.0, 15.0, 15.0]])
+    E, F = pot.energy_forces(*_dev(pos, [1, 0, 0]), L)
+    E0, F0 = oracle.energy_forces(pos, [1, 0, 0], L, cf.model, w)
+    assert abs(E.item() - E0) <= 1e-5 * abs(E0)
+    np.testing.assert_allclose(F.cpu().numpy(), F0, atol=1e-5 * np.abs(F0).max())
+    assert np.all(F.cpu().numpy()[2] == 0.0)
+    pot.close()
+
+
+def test_autograd_function():
+    from paper_2303_08169_amd.potential import EnergyForces
+    cf, pos, z, L, w = system("nh3_64_l1")
+    pot = _potential(cf, w, "fp32")
+    P, Z = _dev(pos, z)
+    P.requires_grad_(True)
+    E = EnergyForces.apply(P, pot, Z, L)
+    E.sum().backward()
+    _, F = pot.energy_forces(P.detach(), Z, L)
+    np.testing.assert_allclose(P.grad.cpu().numpy(), -F.cpu().numpy(), rtol=0, atol=0)
+    pot.close()
