@@ -126,6 +126,60 @@ def errors(sample, F_gpu, Ei_gpu):
             "sample_atoms": int(len(a)), "sample_centres": int(len(c))}
 
 
+def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
+    """NVE run through nq_step in chunks of `chunk` graph-replayed steps; stops at
+    the first chunk that reports an error (e.g. two atoms closer than 0.1 A)."""
+    import numpy as np
+    import torch
+
+    from paper_2303_08169_amd import binding as B
+    from paper_2303_08169_amd.binding import NQError
+    from paper_2303_08169_amd.potential import Potential
+    from synth import weight_blob
+    from synth.nh3 import masses, maxwell_boltzmann
+
+    segs, _ = B.weight_layout(B.make_desc(cf.model, args.precision))
+    w = weight_blob(cf.weight_seed, segs)
+    pot = Potential(cf.model, w, args.precision)
+    dev = torch.device("cuda", 0)
+    P = torch.tensor(pos, device=dev)
+    V = torch.tensor(maxwell_boltzmann(z, 300.0, 200), device=dev)
+    IM = torch.tensor(1.0 / masses(z), device=dev)
+    Z = torch.tensor(z, dtype=torch.int32, device=dev)
+    E, F = pot.energy_forces(P, Z, box)
+    ep = torch.zeros(chunk, dtype=torch.float64, device=dev)
+    ek = torch.zeros(chunk, dtype=torch.float64, device=dev)
+    epot, ekin, err = [], [], None
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    done = 0
+    while done < args.md:
+        n = min(chunk, args.md - done)
+        try:
+            pot.step(P, V, IM, Z, box, dt_fs, n, F, ep, ek)
+        except NQError as e:
+            err = str(e)
+            break
+        epot.extend(ep[:n].cpu().tolist())
+        ekin.extend(ek[:n].cpu().tolist())
+        done += n
+        log(f"md: {done} steps, E_tot/N = {(epot[-1] + ekin[-1]) / cf.n_atoms:.6f} eV")
+    t1 = time.perf_counter()
+    _, rebuilds = pot.stats() if err is None else (0, -1)
+    etot = np.array(epot) + np.array(ekin)
+    out = {"md_steps_requested": args.md, "md_steps_done": done, "dt_fs": dt_fs, "precision": args.precision,
+           "workload": args.workload, "atoms": cf.n_atoms, "error": err, "rebuilds": rebuilds}
+    if done:
+        t = np.arange(1, done + 1) * dt_fs * 1e-3  # ps
+        slope = np.polyfit(t, (etot - etot[0]) / cf.n_atoms * 1e3, 1)[0] if done > 2 else 0.0
+        out.update({"atom_steps_per_s": cf.n_atoms * done / (t1 - t0), "ms_per_step": (t1 - t0) / done * 1e3,
+                    "drift_meV_per_atom_per_ps": float(slope),
+                    "max_abs_dE_per_atom_meV": float(np.abs(etot - etot[0]).max() / cf.n_atoms * 1e3),
+                    "T_final_K": float(2 * ekin[-1] / (3 * cf.n_atoms - 3) / 8.617333262e-5)})
+    print(json.dumps(out), flush=True)
+    pot.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -136,7 +190,20 @@ def main():
     ap.add_argument("--compare", default="fp32,bf16", help="other precision modes timed alongside")
     ap.add_argument("--cpu-sample-atoms", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--md", type=int, default=0, metavar="STEPS",
+                    help="instead: NVE velocity-Verlet run of STEPS steps (dt 0.5 fs, 300 K) through nq_step")
+    ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
     args = ap.parse_args()
+    if args.copy_calib:
+        import torch
+        src = torch.ones(args.copy_calib * (1 << 20) // 4, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_bytes_per_dispatch": src.numel() * 4}))
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this benchmark measures one GPU; no multi-GPU path is built "
                                    "(spatial decomposition is a design note only)", "n_gpus": args.gpus}))
@@ -151,6 +218,8 @@ def main():
 
     cf = config(args.workload)
     pos, z, box = make_system(cf.n_atoms, cf.seed)
+    if args.md:
+        return md_run(args, cf, pos, z, box)
     desc = B.make_desc(cf.model, args.precision)
     segs, _ = B.weight_layout(desc)
     w = weight_blob(cf.weight_seed, segs)
@@ -211,7 +280,7 @@ def main():
     line["modes"] = modes_out
     line["kernels_top"] = sorted(
         [{"name": k["name"], "ms_per_step": k["ms_total"] / main_res["steps"], "launches": k["count"]}
-         for k in main_res["report"]["kernels"]], key=lambda k: -k["ms_per_step"])[:12]
+         for k in main_res["report"]["kernels"]], key=lambda k: -k["ms_per_step"])
     print(json.dumps(line), flush=True)
 
 

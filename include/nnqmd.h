@@ -143,6 +143,13 @@ nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, in
 nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
                           int64_t cap, int64_t* rows, int64_t* width);
 
+/* Upper bound (bytes) of device memory for the per-edge activations of one
+ * evaluation (default 160 GiB, further capped at 3/4 of the free memory). When
+ * the activations of all edges do not fit, centres are processed in chunks of
+ * consecutive atoms, each chunk through the whole forward and adjoint chain;
+ * results do not depend on the chunking. Synchronises the stream. */
+nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes);
+
 /* Per-kernel timing. While enabled, every kernel launch of nq_energy_forces
  * (not of nq_step's graph) is bracketed by HIP events recorded on the
  * context's stream. nq_timing_report synchronises the stream and writes a JSON

@@ -123,9 +123,9 @@ void neighbor_build_sync(nq_ctx* ctx, const double* pos, int64_t n, const double
   }
   std::vector<int> cnt(n);
   NQ_HIP(hipMemcpy(cnt.data(), nl.nbr_cnt.p, n * sizeof(int), hipMemcpyDeviceToHost));
-  int64_t tot = 0;
-  for (int c : cnt) tot += c;
-  nl.n_entries = tot;
+  nl.entry_prefix.assign(n + 1, 0);
+  for (int64_t a = 0; a < n; ++a) nl.entry_prefix[a + 1] = nl.entry_prefix[a] + cnt[a];
+  nl.n_entries = nl.entry_prefix[n];
   nl.built = true;
   zero_flags(ctx);
 }
@@ -167,8 +167,12 @@ void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int
   sp = span_begin(ctx, "edge_list");
   edges_build_async(ctx, pos, m->dims.rc);
   span_end(ctx, sp);
-  forward_async(ctx, m, species, n, energy, atom_energy);
-  backward_async(ctx, m, n, forces);
+  for (int c = 0; c + 1 < (int)ctx->ws.chunks.size(); ++c) {
+    chunk_view_async(ctx, c);
+    forward_async(ctx, m, species, atom_energy);
+    backward_async(ctx, m);
+  }
+  finish_async(ctx, m, energy, forces);
 }
 
 }  // namespace
@@ -243,6 +247,8 @@ void nq_model_destroy(nq_model* model) {
     if (ctx->ws.model == model) {
       ctx->ws.model = nullptr;
       ctx->ws.cap = 0;
+      ctx->ws.cap_all = 0;
+      ctx->ws.chunks.clear();
       ctx->ws.bufs.clear();
     }
     if (ctx->graph_exec) {
@@ -295,6 +301,7 @@ nq_status nq_step(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, 
     std::vector<const void*> key = {model,  pos,  vel,  inv_mass, species, forces,
                                     epot,   ekin, (const void*)(intptr_t)n,
                                     (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
+                                    (const void*)(intptr_t)ctx->ws.chunks.size(),
                                     ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p};
     double dtkey;
     std::memcpy(&dtkey, &dt_fs, sizeof(double));
@@ -383,8 +390,9 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     const Workspace& ws = ctx->ws;
     NQ_REQUIRE(ws.model == model && ws.nedge.p, NQ_ERR_ARG, "no evaluation of this model yet");
     const Dims& d = model->dims;
-    int ne = 0;
-    NQ_HIP(hipMemcpyAsync(&ne, ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    int ne = 0, ne_all = 0;
+    NQ_HIP(hipMemcpyAsync(&ne, ws.v_nedge, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    NQ_HIP(hipMemcpyAsync(&ne_all, ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     NQ_HIP(hipStreamSynchronize(ctx->stream));
     const std::string s(name);
     const float* src = nullptr;
@@ -399,10 +407,10 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     else if (s == "h0") { src = ws.h0; w = ws.K0p; }
     else if (s == "we1") { src = ws.we1; w = 2 * d.NW; }
     else if (s == "eij") { src = ws.eij; w = 1; }
-    else if (s == "g") { src = reinterpret_cast<const float*>(ws.gr); w = 4; }
+    else if (s == "g") { src = reinterpret_cast<const float*>(ws.gr); w = 4; r = ne_all; }
     else if (s == "gu") { src = ws.gu; w = 1; }
     else if (s == "gY") { src = ws.gY; w = 16; }
-    else if ((t = layer("gamma")) >= 1 && t <= d.T) { src = ws.gam[t]; w = d.NY * d.C; r = ws.n_atoms; }
+    else if ((t = layer("gamma")) >= 1 && t <= d.T) { src = ws.gam[t]; w = d.NY * d.C; r = ws.v_n; }
     else if ((t = layer("s")) >= 1 && t <= d.T) { src = ws.s[t]; w = d.nscal * d.C; }
     else if ((t = layer("V")) >= 1 && t < d.T) { src = ws.V[t]; w = d.NY * d.C; }
     else if ((t = layer("x")) >= 0 && t <= d.T) { src = ws.x[t]; w = d.D; }
@@ -412,6 +420,21 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     NQ_REQUIRE(r * w <= cap, NQ_ERR_CAPACITY, "output too small");
     NQ_HIP(hipMemcpyAsync(out, src, (size_t)r * w * 4, hipMemcpyDeviceToDevice, ctx->stream));
     NQ_HIP(hipStreamSynchronize(ctx->stream));
+  });
+}
+
+nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && bytes > 0, NQ_ERR_ARG, "bad budget");
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->ws_budget = bytes;
+    ctx->ws.chunks.clear();  // re-plan at the next call
+    ctx->ws.model = nullptr;
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+      ctx->graph_key.clear();
+    }
   });
 }
 

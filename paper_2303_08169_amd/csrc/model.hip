@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstring>
 
+#include "cg_const.hpp"
 #include "nq_internal.hpp"
 
 namespace nq {
@@ -246,6 +247,41 @@ void upload_lin(Lin& L, const double* W, int fin, int fout) {
   NQ_HIP(hipMemcpy(L.bf_bwd.p, bb.data(), bb.size() * 2, hipMemcpyHostToDevice));
 }
 
+// Channel-mixing weights of one layer: per l3 a [P_l3*C, C] block W (rows (p, c),
+// columns c'), stored natural and with every block transposed to [C, P_l3*C],
+// in FP32 and as BF16 hi | lo halves.
+void upload_mix(MixW& M, const Dims& d, const std::vector<double>& w) {
+  const size_t n = w.size();
+  M.n = (int64_t)n;
+  std::vector<float> fN(n), fT(n);
+  std::vector<uint16_t> bN(2 * n), bT(2 * n);
+  size_t off = 0;
+  for (int l3 = 0; l3 <= d.L; ++l3) {
+    const int rows = d.path_l3_count[l3] * d.C, C = d.C;
+    for (int r = 0; r < rows; ++r)
+      for (int q = 0; q < C; ++q) {
+        const double v = w[off + (size_t)r * C + q];
+        const uint16_t hi = bf16_bits_rne(v), lo = bf16_bits_rne(v - bf16_value(hi));
+        const size_t in = off + (size_t)r * C + q, it = off + (size_t)q * rows + r;
+        fN[in] = (float)v;
+        fT[it] = (float)v;
+        bN[in] = hi;
+        bN[n + in] = lo;
+        bT[it] = hi;
+        bT[n + it] = lo;
+      }
+    off += (size_t)rows * C;
+  }
+  M.fN.ensure(n * 4);
+  M.fT.ensure(n * 4);
+  M.bN.ensure(n * 4);
+  M.bT.ensure(n * 4);
+  NQ_HIP(hipMemcpy(M.fN.p, fN.data(), n * 4, hipMemcpyHostToDevice));
+  NQ_HIP(hipMemcpy(M.fT.p, fT.data(), n * 4, hipMemcpyHostToDevice));
+  NQ_HIP(hipMemcpy(M.bN.p, bN.data(), n * 4, hipMemcpyHostToDevice));
+  NQ_HIP(hipMemcpy(M.bT.p, bT.data(), n * 4, hipMemcpyHostToDevice));
+}
+
 }  // namespace
 
 }  // namespace nq
@@ -256,6 +292,7 @@ nq_model::~nq_model() {
   for (auto& v : lat)
     for (auto* p : v) delete p;
   for (auto* p : edge) delete p;
+  for (auto* p : mixw) delete p;
 }
 
 namespace nq {
@@ -295,10 +332,9 @@ nq_model* model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* w, 
     // W_V0 and W_env^1 share their input x0: store them side by side.
     std::vector<double> cat((size_t)d.D * 2 * d.NW);
     const double* Wv0 = next(fi, fo);
-    std::vector<double> mixes;
     m->env.assign(d.T, nullptr);
     m->lat.assign(d.T, {});
-    m->mix_off.assign(d.T, -1);
+    m->mixw.assign(d.T, nullptr);
     for (int t = 1; t <= d.T; ++t) {
       const double* We = next(fi, fo);
       if (t == 1) {
@@ -318,11 +354,13 @@ nq_model* model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* w, 
         upload_lin(*m->lat[t - 1].back(), Wl, fi, fo);
       }
       if (t < d.T) {
-        m->mix_off[t - 1] = (int64_t)mixes.size();
+        std::vector<double> mixes;
         for (int l3 = 0; l3 <= d.L; ++l3) {
           const double* Wm = next(fi, fo);
           mixes.insert(mixes.end(), Wm, Wm + (size_t)fi * fo);
         }
+        m->mixw[t - 1] = new MixW();
+        upload_mix(*m->mixw[t - 1], d, mixes);
       }
     }
     for (int k = 0; k < d.n_edge; ++k) {
@@ -335,13 +373,34 @@ nq_model* model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* w, 
     for (int k = 0; k < fi; ++k) wo[k] = (float)Wo[k];
     m->wout.ensure(wo.size() * 4);
     NQ_HIP(hipMemcpy(m->wout.p, wo.data(), wo.size() * 4, hipMemcpyHostToDevice));
-    std::vector<float> mf(mixes.begin(), mixes.end());
-    m->mix.ensure(std::max<size_t>(mf.size(), 1) * 4);
-    if (!mf.empty()) NQ_HIP(hipMemcpy(m->mix.p, mf.data(), mf.size() * 4, hipMemcpyHostToDevice));
     CGTable cg;
     derive_cg(cg);
-    m->cg.ensure(sizeof(CGTable));
-    NQ_HIP(hipMemcpy(m->cg.p, &cg, sizeof(CGTable), hipMemcpyHostToDevice));
+    // algorithmic FLOPs per edge of each layer's tensor product (2 per multiply-add
+    // over the non-zero coupling coefficients, channel mixing as dense products)
+    for (int t = 1; t <= d.T; ++t) {
+      double cgf = 0.0, mixf = 0.0;
+      for (int p = 0; p < d.n_paths; ++p) {
+        const int l1 = d.paths[p][0], l2 = d.paths[p][1], l3 = d.paths[p][2];
+        if (t == d.T && l3 != 0) continue;
+        int nnz = 0;
+        for (int a = 0; a < 2 * l1 + 1; ++a)
+          for (int b = 0; b < 2 * l2 + 1; ++b)
+            for (int c = 0; c < 2 * l3 + 1; ++c) nnz += cg.v[l1][l2][l3][a][b][c] != 0.f;
+        cgf += 2.0 * nnz * d.C;
+        if (t < d.T) mixf += 2.0 * (2 * l3 + 1) * d.C * d.C;
+      }
+      m->tp_flop_fwd.push_back(cgf + mixf);
+      m->tp_flop_bwd.push_back(2.0 * cgf + mixf);
+    }
+    // the kernels carry the compile-time table; it must agree with this derivation
+    for (int a = 0; a <= kMaxL; ++a)
+      for (int b = 0; b <= kMaxL; ++b)
+        for (int c = 0; c <= kMaxL; ++c)
+          for (int i = 0; i < 5; ++i)
+            for (int j = 0; j < 5; ++j)
+              for (int k = 0; k < 5; ++k)
+                NQ_REQUIRE(std::fabs(cg.v[a][b][c][i][j][k] - kCG.v[a][b][c][i][j][k]) < 1e-6f, NQ_ERR_DEVICE,
+                           "compile-time coupling table disagrees with the host derivation");
   } catch (...) {
     delete m;
     throw;

@@ -370,13 +370,13 @@ void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut) {
                                                          ws.ecnt.as<int>());
   k_scan_block<<<1, 1024, 0, s>>>(ws.ecnt.as<int>(), ws.eoff.as<int>(), nullptr, n, nullptr, 0);
   // the total edge count lives in eoff[n]
-  k_set_edge_count<<<1, 1, 0, s>>>(ws.eoff.as<int>() + n, ws.nedge.as<int>(), ws.cap, nl.flags.as<int>());
+  k_set_edge_count<<<1, 1, 0, s>>>(ws.eoff.as<int>() + n, ws.nedge.as<int>(), ws.cap_all, nl.flags.as<int>());
   k_edge_fill<<<blocks, kWave * kRowsPerBlock, 0, s>>>(pos, n, nl.box[0], nl.box[1], nl.box[2], rc2,
                                                         nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max,
-                                                        ws.eoff.as<int>(), ws.cap, ws.ei.as<int>(),
+                                                        ws.eoff.as<int>(), ws.cap_all, ws.ei.as<int>(),
                                                         ws.ej.as<int>(), ws.rij.as<float4>(),
                                                         nl.flags.as<int>());
-  k_edge_rev<<<cdiv(ws.cap, 256), 256, 0, s>>>(ws.nedge.as<int>(), ws.ei.as<int>(), ws.ej.as<int>(),
+  k_edge_rev<<<cdiv(ws.cap_all, 256), 256, 0, s>>>(ws.nedge.as<int>(), ws.ei.as<int>(), ws.ej.as<int>(),
                                                ws.eoff.as<int>(), ws.rev.as<int>());
   NQ_HIP(hipGetLastError());
 }

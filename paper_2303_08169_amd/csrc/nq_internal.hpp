@@ -89,6 +89,12 @@ struct Lin {
   DevBuf f32_fwd, f32_bwd, bf_fwd, bf_bwd;
 };
 
+// Channel-mixing weights of one layer (see upload_mix).
+struct MixW {
+  int64_t n = 0;               // floats per copy
+  DevBuf fN, fT, bN, bT;       // FP32 natural / transposed, BF16 [hi | lo] natural / transposed
+};
+
 // Dense real coupling tables C^(l1,l2,l3)[m1][m2][m3], indexed by path triple.
 struct CGTable {
   float v[kMaxL + 1][kMaxL + 1][kMaxL + 1][2 * kMaxL + 1][2 * kMaxL + 1][2 * kMaxL + 1];
@@ -106,9 +112,8 @@ struct nq_model {
   std::vector<std::vector<nq::Lin*>> lat;   // latent layers per layer t (index t-1)
   std::vector<nq::Lin*> edge;               // hidden edge-MLP layers
   nq::DevBuf wout;                          // [edge_last] f32 final edge weights
-  nq::DevBuf mix;                           // per layer t<T: concatenated W_mix^t_l3, f32
-  std::vector<int64_t> mix_off;             // offset (floats) of layer t's mix block
-  nq::DevBuf cg;                            // CGTable on the device
+  std::vector<nq::MixW*> mixw;              // per layer t < T (index t-1)
+  std::vector<double> tp_flop_fwd, tp_flop_bwd;  // algorithmic FLOPs per edge of each layer's tensor product
   ~nq_model();
 };
 
@@ -121,6 +126,7 @@ struct NbrList {
   int nc[3] = {0, 0, 0};
   int k_max = 0;
   int64_t n_entries = 0;  // total skin-list entries at the last host-visible build
+  std::vector<int64_t> entry_prefix;  // prefix sums of the row counts at that build (host)
   bool built = false;
   DevBuf cell_count, cell_start, cell_fill, cell_atoms, atom_cell;
   DevBuf nbr, nbr_cnt, pos_ref;
@@ -129,17 +135,28 @@ struct NbrList {
   DevBuf flags;
 };
 
-// Per-edge workspace of the layered pipeline, sized for `cap` edges.
+// Per-edge workspace of the layered pipeline. The edge list of the whole
+// system holds up to cap_all edges; the per-edge activations hold `cap` edges,
+// one chunk of consecutive centres at a time (one chunk covers the whole system
+// when it fits the memory budget).
 struct Workspace {
-  int64_t cap = 0;
+  int64_t cap = 0;       // edges per chunk (activation buffers)
+  int64_t cap_all = 0;   // edges of the whole system (edge list, per-edge gradients)
   int64_t n_atoms = 0;
   const nq_model* model = nullptr;
-  DevBuf ecnt, eoff, ei, ej, rev, rij, nedge;  // edge list (model independent)
-  std::vector<std::unique_ptr<DevBuf>> bufs;   // model-dependent buffers
+  DevBuf ecnt, eoff, ei, ej, rev, rij, nedge;  // edge list of the whole system
+  DevBuf c_ei, c_ej, c_rij, c_eoff, c_nedge;    // chunk-local copies (chunked mode)
+  DevBuf grbuf;                                 // dE/dr_ij of every edge
+  std::vector<std::unique_ptr<DevBuf>> bufs;    // model-dependent buffers
+  std::vector<int64_t> chunks;                  // centre boundaries a_0 = 0 < a_1 < ... = n
   int K0p = 0, maxw = 0;
+  // current chunk view: centres [v_a0, v_a0 + v_n), edges renumbered from 0
+  int64_t v_a0 = 0, v_n = 0;
+  const int *v_nedge = nullptr, *v_ei = nullptr, *v_ej = nullptr, *v_eoff = nullptr, *v_e0 = nullptr;
+  const float4* v_rij = nullptr;
   float *geo = nullptr, *h0 = nullptr, *we1 = nullptr, *eij = nullptr;
   float *gx = nullptr, *gh[2] = {nullptr, nullptr}, *gs = nullptr, *gv[2] = {nullptr, nullptr};
-  float *ggc = nullptr, *gew = nullptr, *gY = nullptr, *gu = nullptr;
+  float *ggc = nullptr, *ggam = nullptr, *gew = nullptr, *gY = nullptr, *gu = nullptr;
   float4* gr = nullptr;
   double *atomE = nullptr, *esum = nullptr;
   std::vector<float*> a_tb, a_edge, x, gam, s, V, e;
@@ -171,6 +188,7 @@ struct nq_ctx {
   std::vector<const void*> graph_key;
   nq::DevBuf md_scratch;
   int64_t last_edges = 0;
+  int64_t ws_budget = (int64_t)160 << 30;  // bytes allowed for per-edge activations
   // per-launch timing with HIP events on the context's stream
   bool timing = false;
   std::vector<nq::Span> spans;
@@ -192,10 +210,11 @@ void weight_layout(const nq_model_desc& d, std::vector<std::pair<int64_t, int64_
 void derive_cg(CGTable& t);
 
 // ---- pipeline (forward.hip / backward.hip)
-void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms);
-void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64_t n,
-                   double* energy, double* atom_energy);
-void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces);
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms);
+void chunk_view_async(nq_ctx* ctx, int chunk);
+void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy);
+void backward_async(nq_ctx* ctx, const nq_model* m);
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces);
 
 // ---- MD (md.hip)
 void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass,

@@ -19,6 +19,7 @@
 // atomics are needed and the result is deterministic.
 #include <cmath>
 
+#include "cg_const.hpp"
 #include "gemm.hpp"
 #include "nq_internal.hpp"
 
@@ -29,12 +30,6 @@ namespace {
 constexpr int kGeo = 16;  // geo row: d, u, rhat(3), Y(9), pad
 constexpr int kGeoY = 5;
 
-__device__ inline const float* cg_at(const float* cg, int l1, int l2, int l3) {
-  return cg + ((l1 * (kMaxL + 1) + l2) * (kMaxL + 1) + l3) * (2 * kMaxL + 1) * (2 * kMaxL + 1) * (2 * kMaxL + 1);
-}
-__device__ inline float cg_val(const float* t, int m1, int m2, int m3) {
-  return t[(m1 * (2 * kMaxL + 1) + m2) * (2 * kMaxL + 1) + m3];
-}
 
 // Real spherical harmonics, component normalised, order l=1: (x,y,z);
 // l=2: (xy, yz, 3z^2-1, xz, x^2-y^2) with the factors below.
@@ -71,7 +66,7 @@ __device__ inline void envelope(float x, int p, float& u, float& du) {
 
 // ------------------------------------------------------------------ geometry
 __global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __restrict__ rij,
-                           const int* __restrict__ ei, const int* __restrict__ ej,
+                           const int* __restrict__ ei, const int* __restrict__ ej, int64_t a0,
                            const int32_t* __restrict__ species, int S, int nb, int p, float rc,
                            int K0p, float* __restrict__ geo, float* __restrict__ h0, int* __restrict__ flags) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -94,7 +89,7 @@ __global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __rest
   g[14] = 0.f;
   g[15] = 0.f;
   float* h = h0 + e * K0p;
-  const int zi = species[ei[e]], zj = species[ej[e]];
+  const int zi = species[a0 + ei[e]], zj = species[ej[e]];
   if (zi < 0 || zi >= S || zj < 0 || zj >= S) flags[5] = 1;
   for (int k = 0; k < S; ++k) {
     h[k] = (k == zi) ? 1.f : 0.f;
@@ -186,75 +181,236 @@ __device__ inline void load_vprev(bool first, int64_t e, int c, int C, const flo
   }
 }
 
-// Forward tensor product of one layer: s (scalar paths) and, for t < T, the
-// mixed features V_t. Block = (256 / C) edges x C channels.
+// Coupling paths of one l3 group: count, offsets of their components in the
+// full T list, and the offset of the group's mixing block (in units of C*C).
+struct PathInfo {
+  int np[3];
+  int toff[3][4];
+  int moff[3];
+};
+
 template <int LMAX>
+constexpr PathInfo make_path_info() {
+  PathInfo pi{};
+  int toff = 0;
+  for (int l1 = 0; l1 <= LMAX; ++l1)
+    for (int l2 = 0; l2 <= LMAX; ++l2)
+      for (int l3 = 0; l3 <= LMAX; ++l3)
+        if ((l1 - l2 <= l3) && (l2 - l1 <= l3) && (l3 <= l1 + l2) && ((l1 + l2 + l3) % 2 == 0)) {
+          pi.toff[l3][pi.np[l3]++] = toff;
+          toff += 2 * l3 + 1;
+        }
+  int o = 0;
+  for (int l3 = 0; l3 <= LMAX; ++l3) {
+    pi.moff[l3] = o;
+    o += pi.np[l3];
+  }
+  return pi;
+}
+
+template <int LMAX> struct Paths {
+  static constexpr PathInfo pi = make_path_info<LMAX>();
+};
+
+// Channel-mixing weights of one layer as the matrix-core kernels read them.
+struct MixPtrs {
+  const float* fN;   // FP32 [(p, c)][c'] per l3 block
+  const float* fT;   // FP32 [c'][(p, c)] per l3 block
+  const bf16* bN;    // BF16 hi | lo, natural
+  const bf16* bT;    // BF16 hi | lo, transposed
+  int64_t n;         // elements per copy (offset of the lo half)
+};
+
+__device__ inline void load8(const float* p, float* v) {
+  *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(p);
+  *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(p + 4);
+}
+
+__device__ inline bf16x8 to_bf16x8(const float* v) {
+  bf16x8 r;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) r[k] = (bf16)v[k];
+  return r;
+}
+
+// One 16x16 output tile of a small product on the matrix cores, accumulating
+// over K: A(r, k) comes from `afetch(k)` (this lane's row, 1 or 8 values from
+// LDS), B(k, n) from `bptr(k)` (this lane's column, contiguous in k, global).
+template <int KIND, class AF, class BP>
+__device__ inline floatx4 tile_mma(int K, int lane, int64_t lo_off, bool bvalid, AF&& afetch, BP&& bptr) {
+  floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+  if constexpr (KIND == G_F32) {
+    for (int kk = 0; kk < K; kk += 4) {
+      const int k = kk + (lane >> 4);
+      float a = 0.f, b = 0.f;
+      if (k < K) {
+        afetch(k, &a);
+        if (bvalid) b = *static_cast<const float*>(bptr(k));
+      }
+      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, acc, 0, 0, 0);
+    }
+  } else {
+    for (int kk = 0; kk < K; kk += 32) {
+      const int k = kk + (lane >> 4) * 8;
+      float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+      bf16x8 bhi = {}, blo = {};
+      if (k < K) {
+        afetch(k, v);
+        if (bvalid) {
+          const bf16* bp = static_cast<const bf16*>(bptr(k));
+          bhi = *reinterpret_cast<const bf16x8*>(bp);
+          if constexpr (KIND == G_BF16X3) blo = *reinterpret_cast<const bf16x8*>(bp + lo_off);
+        }
+      }
+      if constexpr (KIND == G_BF16) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(to_bf16x8(v), bhi, acc, 0, 0, 0);
+      } else {
+        bf16x8 ahi, alo;
+        split_bf16(v, ahi, alo);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bhi, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, blo, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bhi, acc, 0, 0, 0);
+      }
+    }
+  }
+  return acc;
+}
+
+// Forward channel mixing of one edge group on the matrix cores. For each l3:
+// rows (edge, m), K = (path p, channel c), columns c':
+// V_t[e][l3 m][c'] = sum_{p, c} T[e][toff(p) + m][c] W_l3[(p, c)][c'].
+template <int KIND, int LMAX>
+__device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int64_t ne, const MixPtrs& W,
+                               float* __restrict__ vout) {
+  constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
+  const PathInfo& pi = Paths<LMAX>::pi;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int tile = 0;
+#pragma unroll
+  for (int l3 = 0; l3 <= LMAX; ++l3) {
+    const int nm = 2 * l3 + 1, R = epb * nm, RT = (R + 15) / 16, CT = (C + 15) / 16, K = pi.np[l3] * C;
+    const int64_t woff = (int64_t)pi.moff[l3] * C * C;
+    for (int rt = 0; rt < RT; ++rt)
+      for (int ct = 0; ct < CT; ++ct, ++tile) {
+        if ((tile & 3) != wave) continue;
+        const int r = rt * 16 + (lane & 15);
+        const bool rv = r < R;
+        const int el = rv ? r / nm : 0, m = rv ? r % nm : 0;
+        const int n = ct * 16 + (lane & 15);
+        auto af = [&](int k, float* v) {
+          if (!rv) return;
+          const float* src = Tl + (el * NT + pi.toff[l3][k / C] + m) * C + (k % C);
+          if constexpr (KIND == G_F32) v[0] = *src; else load8(src, v);
+        };
+        auto bp = [&](int k) -> const void* {
+          if constexpr (KIND == G_F32) return W.fT + woff + (int64_t)n * K + k;
+          else return W.bT + woff + (int64_t)n * K + k;
+        };
+        const floatx4 acc = tile_mma<KIND>(K, lane, W.n, n < C, af, bp);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = rt * 16 + 4 * (lane >> 4) + q;
+          if (rr < R && n < C) {
+            const int64_t e = e0 + rr / nm;
+            if (e < ne) vout[(e * NY + l3 * l3 + rr % nm) * C + n] = acc[q];
+          }
+        }
+      }
+  }
+}
+
+// Adjoint of the channel mixing for one edge group, into LDS:
+// gT[e][toff(p) + m][c] = sum_{c'} gV[e][l3 m][c'] W_l3[(p, c)][c'].
+template <int KIND, int LMAX>
+__device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, const MixPtrs& W) {
+  constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
+  const PathInfo& pi = Paths<LMAX>::pi;
+  const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int tile = 0;
+#pragma unroll
+  for (int l3 = 0; l3 <= LMAX; ++l3) {
+    const int nm = 2 * l3 + 1, R = epb * nm, RT = (R + 15) / 16, N = pi.np[l3] * C, CT = (N + 15) / 16;
+    const int64_t woff = (int64_t)pi.moff[l3] * C * C;
+    for (int rt = 0; rt < RT; ++rt)
+      for (int ct = 0; ct < CT; ++ct, ++tile) {
+        if ((tile & 3) != wave) continue;
+        const int r = rt * 16 + (lane & 15);
+        const bool rv = r < R;
+        const int el = rv ? r / nm : 0, m = rv ? r % nm : 0;
+        const int n = ct * 16 + (lane & 15);
+        auto af = [&](int k, float* v) {
+          if (!rv) return;
+          const float* src = gVl + (el * NY + l3 * l3 + m) * C + k;
+          if constexpr (KIND == G_F32) v[0] = *src; else load8(src, v);
+        };
+        auto bp = [&](int k) -> const void* {
+          if constexpr (KIND == G_F32) return W.fN + woff + (int64_t)n * C + k;
+          else return W.bN + woff + (int64_t)n * C + k;
+        };
+        const floatx4 acc = tile_mma<KIND>(C, lane, W.n, n < N, af, bp);
+        const int p = n / C, c = n % C;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int rr = rt * 16 + 4 * (lane >> 4) + q;
+          if (rr < R && n < N) gTl[((rr / nm) * NT + pi.toff[l3][p] + rr % nm) * C + c] = acc[q];
+        }
+      }
+  }
+}
+
+// Forward tensor product of one layer: s (scalar paths) and, for t < T, the
+// mixed features V_t. A workgroup loops over groups of (256 / C) edges x C
+// channels; one thread computes all coupling paths of one (edge, channel) in
+// registers (zero coefficients skipped at compile time), the group's T is
+// staged in LDS and mixed across channels on the matrix cores.
+template <int KIND, int LMAX>
 __global__ __launch_bounds__(256) void k_tp_fwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
                                                 const float* __restrict__ geo, int C, int first, int last,
                                                 const float* __restrict__ we1, int ldwe,
                                                 const float* __restrict__ vprev, const float* __restrict__ gam,
-                                                const float* __restrict__ cg, float* __restrict__ s, int lds,
-                                                const float* __restrict__ mix, float* __restrict__ vout) {
+                                                float* __restrict__ s, int lds, MixPtrs W, float* __restrict__ vout) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ float Tl[256 * NT];
+  __shared__ __attribute__((aligned(16))) float Tl[256 * NT];
   const int epb = 256 / C;
   const int el = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t e = (int64_t)blockIdx.x * epb + el;
-  const bool valid = e < *nedge_p;
-  float T[NT];
+  const int64_t ne = *nedge_p;
+  const int64_t ngroups = (ne + epb - 1) / epb;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t e = grp * epb + el;
+    const bool valid = e < ne;
+    float T[NT];
 #pragma unroll
-  for (int k = 0; k < NT; ++k) T[k] = 0.f;
-  if (valid) {
-    const float* Y = geo + e * kGeo + kGeoY;
-    float V[NY], G[NY];
-    load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
-    const int64_t i = ei[e];
+    for (int k = 0; k < NT; ++k) T[k] = 0.f;
+    if (valid) {
+      const float* Y = geo + e * kGeo + kGeoY;
+      float V[NY], G[NY];
+      load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
+      const int64_t i = ei[e];
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
-    for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int qs, int) {
-      const float* t = cg_at(cg, l1, l2, l3);
+      for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
+      for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
-      for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
-        float a = 0.f;
+        for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+          float a = 0.f;
 #pragma unroll
-        for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+          for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
 #pragma unroll
-          for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) a += cg_val(t, m1, m2, m3) * V[l1 * l1 + m1] * G[l2 * l2 + m2];
-        T[toff + m3] = a;
-      }
-      if (l3 == 0) s[e * lds + qs * C + c] = T[toff];
-    });
-  }
-  if (last) return;
-  // channel mixing: V_t[l3 m][c'] = sum_{p in l3} sum_c T_p[m][c] W_l3[(p, c), c']
-#pragma unroll
-  for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * C + c] = T[k];
-  __syncthreads();
-  if (!valid) return;
-  int moff[3];
-  {
-    int o = 0;
-    int cnt[3] = {0, 0, 0};
-    for_paths<LMAX>(false, [&](int, int, int l3, int, int, int) { cnt[l3]++; });
-#pragma unroll
-    for (int l3 = 0; l3 <= LMAX; ++l3) {
-      moff[l3] = o;
-      o += cnt[l3] * C * C;
+            for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+              const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
+              if (cgv != 0.f) a += cgv * V[l1 * l1 + m1] * G[l2 * l2 + m2];
+            }
+          T[toff + m3] = a;
+        }
+        if (l3 == 0) s[e * lds + qs * C + c] = T[toff];
+      });
     }
+    if (last) continue;
+#pragma unroll
+    for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * C + c] = T[k];
+    __syncthreads();
+    mix_fwd<KIND, LMAX>(Tl, epb, C, grp * epb, ne, W, vout);
+    __syncthreads();
   }
-  float out[NY];
-#pragma unroll
-  for (int k = 0; k < NY; ++k) out[k] = 0.f;
-  for_paths<LMAX>(false, [&](int, int, int l3, int toff, int, int pidx) {
-    const float* W = mix + moff[l3] + (int64_t)pidx * C * C;
-    for (int cc = 0; cc < C; ++cc) {
-      const float w = W[cc * C + c];
-#pragma unroll
-      for (int m = 0; m < 2 * l3 + 1; ++m) out[l3 * l3 + m] += Tl[(el * NT + toff + m) * C + cc] * w;
-    }
-  });
-#pragma unroll
-  for (int lm = 0; lm < NY; ++lm) vout[(e * NY + lm) * C + c] = out[lm];
 }
 
 // ------------------------------------------------------------------ energy
@@ -332,120 +488,108 @@ __global__ __launch_bounds__(256) void k_rowdot_gu(const int* __restrict__ nedge
   if (valid && l == 0) gu[e] += c * acc;
 }
 
-// Adjoint of one layer's tensor product (and of the channel mixing for t < T).
-// Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i, and either
-// dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and the w0 part
-// of dE/dY into gY.
-template <int LMAX>
+// Adjoint of one layer's tensor product (and of the channel mixing for t < T,
+// on the matrix cores through LDS). Writes the per-edge contributions
+// ggc[e][lm][c] to dE/dGamma_i, and either dE/dV_{t-1} (t > 1) or, for t = 1,
+// dE/dw0 into gew[:, 0:NW] and the w0 part of dE/dY into gY.
+template <int KIND, int LMAX>
 __global__ __launch_bounds__(256) void k_tp_bwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
                                                 const float* __restrict__ geo, int C, int first, int last,
                                                 const float* __restrict__ we1, int ldwe,
                                                 const float* __restrict__ vprev, const float* __restrict__ gam,
-                                                const float* __restrict__ cg, const float* __restrict__ gs,
-                                                int ldgs, const float* __restrict__ gvin,
-                                                const float* __restrict__ mix, float* __restrict__ ggc,
-                                                float* __restrict__ gvout, float* __restrict__ gew, int ldgew,
-                                                float* __restrict__ gY) {
+                                                const float* __restrict__ gs, int ldgs,
+                                                const float* __restrict__ gvin, MixPtrs W,
+                                                float* __restrict__ ggc, float* __restrict__ gvout,
+                                                float* __restrict__ gew, int ldgew, float* __restrict__ gY) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ float gVl[256 * NY];
+  __shared__ __attribute__((aligned(16))) float gVl[256 * NY];
+  __shared__ __attribute__((aligned(16))) float gTl[256 * NT];
   const int epb = 256 / C;
   const int el = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t e = (int64_t)blockIdx.x * epb + el;
-  const bool valid = e < *nedge_p;
-  if (!last) {
-#pragma unroll
-    for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * C + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
-    __syncthreads();
-  }
-  if (!valid) return;
-  const float* Y = geo + e * kGeo + kGeoY;
-  float V[NY], G[NY], gT[NT];
-  load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
-  const int64_t i = ei[e];
-#pragma unroll
-  for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
-#pragma unroll
-  for (int k = 0; k < NT; ++k) gT[k] = 0.f;
-  int moff[3] = {0, 0, 0};
-  {
-    int o = 0;
-    int cnt[3] = {0, 0, 0};
-    for_paths<LMAX>(false, [&](int, int, int l3, int, int, int) { cnt[l3]++; });
-#pragma unroll
-    for (int l3 = 0; l3 <= LMAX; ++l3) {
-      moff[l3] = o;
-      o += cnt[l3] * C * C;
-    }
-  }
-  for_paths<LMAX>(last, [&](int, int, int l3, int toff, int qs, int pidx) {
-    if (l3 == 0) gT[toff] += gs[e * ldgs + qs * C + c];
+  const int64_t ne = *nedge_p;
+  const int64_t ngroups = (ne + epb - 1) / epb;
+  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+    const int64_t e = grp * epb + el;
+    const bool valid = e < ne;
     if (!last) {
-      const float* W = mix + moff[l3] + (int64_t)pidx * C * C + (int64_t)c * C;
-      for (int cc = 0; cc < C; ++cc) {
-        const float w = W[cc];
 #pragma unroll
-        for (int m = 0; m < 2 * l3 + 1; ++m) gT[toff + m] += gVl[(el * NY + l3 * l3 + m) * C + cc] * w;
+      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * C + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
+      __syncthreads();
+      mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, W);
+      __syncthreads();
+    }
+    if (valid) {
+      const float* Y = geo + e * kGeo + kGeoY;
+      float V[NY], G[NY], gT[NT];
+      load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
+      const int64_t i = ei[e];
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
+#pragma unroll
+      for (int k = 0; k < NT; ++k) gT[k] = last ? 0.f : gTl[(el * NT + k) * C + c];
+      for_paths<LMAX>(last, [&](int, int, int l3, int toff, int qs, int) {
+        if (l3 == 0) gT[toff] += gs[e * ldgs + qs * C + c];
+      });
+      float gV[NY], gG[NY];
+#pragma unroll
+      for (int k = 0; k < NY; ++k) {
+        gV[k] = 0.f;
+        gG[k] = 0.f;
+      }
+      for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int, int) {
+#pragma unroll
+        for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+          const float g = gT[toff + m3];
+#pragma unroll
+          for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+#pragma unroll
+            for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+              const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
+              if (cgv != 0.f) {
+                const float w = cgv * g;
+                gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
+                gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
+              }
+            }
+        }
+      });
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) ggc[(e * NY + lm) * C + c] = gG[lm];
+      if (!first) {
+#pragma unroll
+        for (int lm = 0; lm < NY; ++lm) gvout[(e * NY + lm) * C + c] = gV[lm];
+      } else {
+        // V0[c][lm] = w0[l][c] Y[lm]
+#pragma unroll
+        for (int l = 0; l <= LMAX; ++l) {
+          float gw = 0.f;
+          const float w0 = we1[e * ldwe + l * C + c];
+#pragma unroll
+          for (int m = 0; m < 2 * l + 1; ++m) {
+            gw += gV[l * l + m] * Y[l * l + m];
+            float part = w0 * gV[l * l + m];
+            for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
+            if (c == 0) gY[e * 16 + l * l + m] += part;
+          }
+          gew[e * ldgew + l * C + c] = gw;
+        }
       }
     }
-  });
-  float gV[NY], gG[NY];
-#pragma unroll
-  for (int k = 0; k < NY; ++k) {
-    gV[k] = 0.f;
-    gG[k] = 0.f;
-  }
-  for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int, int) {
-    const float* t = cg_at(cg, l1, l2, l3);
-#pragma unroll
-    for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
-      const float g = gT[toff + m3];
-#pragma unroll
-      for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
-#pragma unroll
-        for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
-          const float w = cg_val(t, m1, m2, m3) * g;
-          gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
-          gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
-        }
-    }
-  });
-#pragma unroll
-  for (int lm = 0; lm < NY; ++lm) ggc[(e * NY + lm) * C + c] = gG[lm];
-  if (!first) {
-#pragma unroll
-    for (int lm = 0; lm < NY; ++lm) gvout[(e * NY + lm) * C + c] = gV[lm];
-    return;
-  }
-  // V0[c][lm] = w0[l][c] Y[lm]
-#pragma unroll
-  for (int l = 0; l <= LMAX; ++l) {
-    float gw = 0.f;
-    const float w0 = we1[e * ldwe + l * C + c];
-#pragma unroll
-    for (int m = 0; m < 2 * l + 1; ++m) {
-      gw += gV[l * l + m] * Y[l * l + m];
-      float part = w0 * gV[l * l + m];
-      for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-      if (c == 0) gY[e * 16 + l * l + m] += part;
-    }
-    gew[e * ldgew + l * C + c] = gw;
+    if (!last) __syncthreads();
   }
 }
 
-// Per-centre adjoint of the environment sum: dGamma_i = nu^-1/2 sum_j ggc[j];
-// then for each edge k of i: de_k[l][c] = sum_m dGamma_i[lm][c] Y_k[lm] and
-// dY_k[lm] += sum_c e_k[l][c] dGamma_i[lm][c].
+// Per-centre adjoint of the environment sum, part 1:
+// dGamma_i[lm][c] = nu^-1/2 sum_{j: (i,j) edge} ggc[(i,j)][lm][c]
+// (one wavefront per centre, lanes as in k_env_fwd).
 template <int NY>
-__global__ __launch_bounds__(256) void k_env_bwd(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
-                                                 const float* __restrict__ ggc, const float* __restrict__ esrc,
-                                                 int lde, const float* __restrict__ geo, int C, float scale,
-                                                 float* __restrict__ gew, int ldgew, int gcol,
-                                                 float* __restrict__ gY) {
+__global__ __launch_bounds__(256) void k_env_reduce(int64_t n, const int* __restrict__ nedge_p,
+                                                    const int* __restrict__ eoff, const float* __restrict__ ggc, int C,
+                                                    float scale, float* __restrict__ ggam) {
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= n) return;
   const int lane = threadIdx.x % 64;
   const int c = lane % C, g = lane / C, G = 64 / C;
-  constexpr int L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
   float acc[NY];
 #pragma unroll
   for (int q = 0; q < NY; ++q) acc[q] = 0.f;
@@ -458,33 +602,43 @@ __global__ __launch_bounds__(256) void k_env_bwd(int64_t n, const int* __restric
       if (lm < NY) acc[q] += ggc[((int64_t)e * NY + lm) * C + c];
     }
 #pragma unroll
-  for (int q = 0; q < NY; ++q) acc[q] *= scale;
-  for (int e = b; e < e1; ++e) {
-    const float* Y = geo + (int64_t)e * kGeo + kGeoY;
-    float part[L + 1];
+  for (int q = 0; q < NY; ++q) {
+    const int lm = g + q * G;
+    if (lm < NY) ggam[(i * NY + lm) * C + c] = acc[q] * scale;
+  }
+}
+
+// Part 2, per (edge k, channel c) of centre i:
+// de_k[l][c] = sum_m dGamma_i[lm][c] Y_k[lm]  -> gew[:, gcol + l*C + c]
+// dY_k[lm] += sum_c e_k[l][c] dGamma_i[lm][c]  (reduced over the C lanes of the edge)
+template <int NY>
+__global__ __launch_bounds__(256) void k_env_bwd_edge(const int* __restrict__ nedge_p, const int* __restrict__ ei,
+                                                      const float* __restrict__ ggam, const float* __restrict__ esrc,
+                                                      int lde, const float* __restrict__ geo, int C,
+                                                      float* __restrict__ gew, int ldgew, int gcol,
+                                                      float* __restrict__ gY) {
+  constexpr int L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
+  const int epb = 256 / C;
+  const int el = threadIdx.x / C, c = threadIdx.x % C;
+  const int64_t e = (int64_t)blockIdx.x * epb + el;
+  if (e >= *nedge_p) return;
+  const int64_t i = ei[e];
+  const float* Y = geo + e * kGeo + kGeoY;
+  float ev[L + 1];
 #pragma unroll
-    for (int l = 0; l <= L; ++l) part[l] = 0.f;
+  for (int l = 0; l <= L; ++l) ev[l] = esrc[e * lde + l * C + c];
 #pragma unroll
-    for (int q = 0; q < NY; ++q) {
-      const int lm = g + q * G;
-      if (lm < NY) {
-        const float y = Y[lm];
-        const int lq = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+  for (int l = 0; l <= L; ++l) {
+    float ge = 0.f;
 #pragma unroll
-        for (int l = 0; l <= L; ++l)
-          if (l == lq) part[l] += acc[q] * y;
-        // dY contribution, reduced over the channels of this group
-        float prod = esrc[(int64_t)e * lde + lq * C + c] * acc[q];
-        for (int o = C / 2; o >= 1; o >>= 1) prod += __shfl_xor(prod, o, C);
-        if (c == 0) gY[(int64_t)e * 16 + lm] += prod;
-      }
+    for (int m = 0; m < 2 * l + 1; ++m) {
+      const float gg = ggam[(i * NY + l * l + m) * C + c];
+      ge += gg * Y[l * l + m];
+      float prod = ev[l] * gg;
+      for (int o = C / 2; o >= 1; o >>= 1) prod += __shfl_xor(prod, o, C);
+      if (c == 0) gY[e * 16 + l * l + m] += prod;
     }
-#pragma unroll
-    for (int l = 0; l <= L; ++l) {
-      float v = part[l];
-      for (int o = C; o < 64; o <<= 1) v += __shfl_xor(v, o, 64);
-      if (g == 0) gew[(int64_t)e * ldgew + gcol + l * C + c] = v;
-    }
+    gew[e * ldgew + gcol + l * C + c] = ge;
   }
 }
 
@@ -499,7 +653,7 @@ __device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, 
 __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __restrict__ geo,
                                const float* __restrict__ gu, const float* __restrict__ gYb,
                                const float* __restrict__ gh0, int ldh0, int boff, int nb, int p, float rc, int NY,
-                               float4* __restrict__ gr) {
+                               const int* __restrict__ e0p, float4* __restrict__ gr) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= *nedge_p) return;
   const float* g = geo + e * kGeo;
@@ -525,7 +679,7 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
   float ax, ay, az;
   sph_grad_dot(gY, x, y, z, ax, ay, az);
   const float rad = ax * x + ay * y + az * z;
-  gr[e] = make_float4(gd * x + (ax - rad * x) * inv, gd * y + (ay - rad * y) * inv, gd * z + (az - rad * z) * inv,
+  gr[*e0p + e] = make_float4(gd * x + (ax - rad * x) * inv, gd * y + (ay - rad * y) * inv, gd * z + (az - rad * z) * inv,
                       0.f);
 }
 
@@ -574,23 +728,17 @@ void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, 
     case 256: launch_gemm_t<KIND, 64, 256, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
     case 352: launch_gemm_t<KIND, X3 ? 32 : 64, 352, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
     case 384:
-      if constexpr (!X3) {
-        launch_gemm_t<KIND, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-        break;
-      }
-      [[fallthrough]];
+      if constexpr (X3) launch_gemm_t<KIND, 32, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+      else launch_gemm_t<KIND, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+      break;
     case 512:
-      if constexpr (!X3) {
-        launch_gemm_t<KIND, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-        break;
-      }
-      [[fallthrough]];
+      if constexpr (X3) launch_gemm_t<KIND, 32, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+      else launch_gemm_t<KIND, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+      break;
     case 704:
-      if constexpr (!X3) {
-        launch_gemm_t<KIND, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep);
-        break;
-      }
-      [[fallthrough]];
+      if constexpr (X3) launch_gemm_t<KIND, 32, 704, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
+      else launch_gemm_t<KIND, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep);
+      break;
     default: throw Error{NQ_ERR_UNSUPPORTED, "no matrix-core kernel for output width " + std::to_string(NP)};
   }
 }
@@ -602,7 +750,7 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
   const int sp = span_begin(ctx, name, 2.0 * L.fin * L.fout, 4.0 * (L.fin + L.fout));
   const int NP = bwd ? L.np_b : L.np_f;
   const int Kp = bwd ? L.kp_b : L.kp_f;
-  const int* nr = ws.nedge.as<int>();
+  const int* nr = ws.v_nedge;
   switch (m->dims.prec) {
     case NQ_PRECISION_BF16:
       launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep);
@@ -630,31 +778,164 @@ Epi e_add(float* o, int ld, int N) { return Epi{E_ADD, o, ld, N, nullptr, 0, nul
 
 unsigned grid_for(int64_t n, int per_block) { return (unsigned)std::max<int64_t>(1, cdiv(n, per_block)); }
 
+// ------------------------------------------------------------------ per-edge launches
+MixPtrs layer_mix(const nq_model* m, int t) {
+  MixPtrs w{nullptr, nullptr, nullptr, nullptr, 0};
+  if (t == m->dims.T) return w;
+  const MixW& M = *m->mixw[t - 1];
+  w.fN = M.fN.as<float>();
+  w.fT = M.fT.as<float>();
+  w.bN = M.bN.as<bf16>();
+  w.bT = M.bT.as<bf16>();
+  w.n = M.n;
+  return w;
+}
+
+// Persistent launches: enough workgroups to fill the chip, each looping over
+// groups of edges.
+unsigned tp_grid(const Workspace& ws, int C) {
+  return (unsigned)std::min<int64_t>(grid_for(ws.cap, 256 / C), 4096);
+}
+
+void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
+  const Dims& d = m->dims;
+  Workspace& ws = ctx->ws;
+  const bool last = t == d.T;
+  const MixPtrs W = layer_mix(m, t);
+  const unsigned grid = tp_grid(ws, d.C);
+  const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1]);
+#define NQ_TPF(K, LM)                                                                                    \
+  k_tp_fwd<K, LM><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, \
+                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.s[t],  \
+                                                  d.nscal * d.C, W, ws.V[t])
+  switch (d.prec * 2 + (d.L == 2)) {
+    case 0: NQ_TPF(G_F32, 1); break;
+    case 1: NQ_TPF(G_F32, 2); break;
+    case 2: NQ_TPF(G_BF16, 1); break;
+    case 3: NQ_TPF(G_BF16, 2); break;
+    case 4: NQ_TPF(G_BF16X3, 1); break;
+    default: NQ_TPF(G_BF16X3, 2); break;
+  }
+#undef NQ_TPF
+  NQ_HIP(hipGetLastError());
+  span_end(ctx, sp);
+}
+
+void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, float* gvout) {
+  const Dims& d = m->dims;
+  Workspace& ws = ctx->ws;
+  const bool last = t == d.T;
+  const MixPtrs W = layer_mix(m, t);
+  const unsigned grid = tp_grid(ws, d.C);
+  const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1]);
+#define NQ_TPB(K, LM)                                                                                     \
+  k_tp_bwd<K, LM><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
+                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.gs,     \
+                                                  d.nscal * d.C, last ? nullptr : gvin, W, ws.ggc, gvout,    \
+                                                  ws.gew, 2 * d.NW, ws.gY)
+  switch (d.prec * 2 + (d.L == 2)) {
+    case 0: NQ_TPB(G_F32, 1); break;
+    case 1: NQ_TPB(G_F32, 2); break;
+    case 2: NQ_TPB(G_BF16, 1); break;
+    case 3: NQ_TPB(G_BF16, 2); break;
+    case 4: NQ_TPB(G_BF16X3, 1); break;
+    default: NQ_TPB(G_BF16X3, 2); break;
+  }
+#undef NQ_TPB
+  NQ_HIP(hipGetLastError());
+  span_end(ctx, sp);
+}
+
+void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
+  const Dims& d = m->dims;
+  Workspace& ws = ctx->ws;
+  const int64_t n = ws.v_n;
+  const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
+  const int lde = t == 1 ? 2 * d.NW : d.NW;
+  const float scale = (float)d.inv_sqrt_nu;
+  int sp = span_begin(ctx, "env_reduce" + std::to_string(t));
+  if (d.L == 1)
+    k_env_reduce<4><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
+                                                              scale, ws.ggam);
+  else
+    k_env_reduce<9><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
+                                                              scale, ws.ggam);
+  span_end(ctx, sp);
+  sp = span_begin(ctx, "env_bwd" + std::to_string(t));
+  if (d.L == 1)
+    k_env_bwd_edge<4><<<grid_for(ws.cap, 256 / d.C), 256, 0, ctx->stream>>>(
+        ws.v_nedge, ws.v_ei, ws.ggam, esrc, lde, ws.geo, d.C, ws.gew, 2 * d.NW, d.NW, ws.gY);
+  else
+    k_env_bwd_edge<9><<<grid_for(ws.cap, 256 / d.C), 256, 0, ctx->stream>>>(
+        ws.v_nedge, ws.v_ei, ws.ggam, esrc, lde, ws.geo, d.C, ws.gew, 2 * d.NW, d.NW, ws.gY);
+  NQ_HIP(hipGetLastError());
+  span_end(ctx, sp);
+}
+
 }  // namespace
 
 // ------------------------------------------------------------------ workspace
-void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms) {
+namespace {
+
+// Bytes of per-edge activation and adjoint buffers per edge of a chunk.
+int64_t bytes_per_edge(const Dims& d, int K0p, int maxw) {
+  int64_t w = kGeo + K0p + 2 * d.NW + 1;  // geo, h0, we1, eij
+  for (int k = 0; k < d.n_tb; ++k) w += d.tb[k];
+  w += d.D;  // x0
+  for (int t = 1; t <= d.T; ++t) {
+    if (t > 1) w += d.NW;
+    w += d.nscal * d.C + d.D;
+    for (int k = 0; k < d.n_lat; ++k) w += d.lat[k];
+    if (t < d.T) w += d.NY * d.C;
+  }
+  for (int k = 0; k < d.n_edge; ++k) w += d.edge[k];
+  w += d.D + 2 * maxw + d.nscal * d.C + 3 * d.NY * d.C + 2 * d.NW + 16 + 1;  // adjoint
+  return w * 4 + 24;  // + chunk-local edge copies
+}
+
+// Per-chunk edge views: chunk-local centre index, neighbour, geometry, offsets.
+__global__ void k_chunk_edges(const int* __restrict__ eoff, int64_t a0, int64_t a1, int64_t cap,
+                              const int* __restrict__ ei, const int* __restrict__ ej, const float4* __restrict__ rij,
+                              int* c_ei, int* c_ej, float4* c_rij, int* c_nedge, int* flags) {
+  const int64_t e0 = eoff[a0], n = (int64_t)eoff[a1] - e0;
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e == 0) {
+    if (n > cap) flags[4] = (int)n;
+    *c_nedge = (int)(n < cap ? n : cap);
+  }
+  if (e >= n || e >= cap) return;
+  c_ei[e] = ei[e0 + e] - (int)a0;
+  c_ej[e] = ej[e0 + e];
+  c_rij[e] = rij[e0 + e];
+}
+
+__global__ void k_chunk_offsets(const int* __restrict__ eoff, int64_t a0, int64_t a1, int* c_eoff) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > a1 - a0) return;
+  c_eoff[i] = eoff[a0 + i] - eoff[a0];
+}
+
+}  // namespace
+
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms) {
   Workspace& ws = ctx->ws;
-  cap = rup(std::max<int64_t>(cap, 1), 128);
-  if (ws.model == m && ws.cap >= cap && ws.n_atoms == n_atoms) return;
+  cap_all = rup(std::max<int64_t>(cap_all, 1), 128);
+  const NbrList& nl = ctx->nl;
+  if (ws.model == m && ws.cap_all >= cap_all && ws.n_atoms == n_atoms && !ws.chunks.empty()) return;
   const Dims& d = m->dims;
   NQ_HIP(hipStreamSynchronize(ctx->stream));
   ws.bufs.clear();
-  ws.cap = cap;
+  ws.cap_all = cap_all;
   ws.n_atoms = n_atoms;
   ws.model = m;
   ws.ecnt.ensure(n_atoms * 4);
   ws.eoff.ensure((n_atoms + 1) * 4);
-  ws.ei.ensure(cap * 4);
-  ws.ej.ensure(cap * 4);
-  ws.rev.ensure(cap * 4);
-  ws.rij.ensure(cap * 16);
+  ws.ei.ensure(cap_all * 4);
+  ws.ej.ensure(cap_all * 4);
+  ws.rev.ensure(cap_all * 4);
+  ws.rij.ensure(cap_all * 16);
+  ws.grbuf.ensure(cap_all * 16);
   ws.nedge.ensure(64);
-  auto fbuf = [&](int64_t rows, int64_t width) -> float* {
-    ws.bufs.emplace_back(new DevBuf());
-    ws.bufs.back()->ensure((size_t)rows * width * 4);
-    return ws.bufs.back()->as<float>();
-  };
   ws.K0p = (int)rup(d.n_in2b, 32);
   int maxw = d.n_in2b;
   for (int k = 0; k < d.n_tb; ++k) maxw = std::max(maxw, d.tb[k]);
@@ -662,6 +943,41 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms) {
   for (int k = 0; k < d.n_edge; ++k) maxw = std::max(maxw, d.edge[k]);
   maxw = std::max(maxw, d.D + d.nscal * d.C);
   ws.maxw = (int)rup(maxw, 16);
+  // Chunks of consecutive centres whose list entries (an upper bound of their
+  // edges, with a margin for rebuilds) fit the activation budget.
+  size_t free_b = 0, total_b = 0;
+  NQ_HIP(hipMemGetInfo(&free_b, &total_b));
+  const int64_t bpe = bytes_per_edge(d, ws.K0p, ws.maxw);
+  int64_t budget = std::min<int64_t>((int64_t)(0.75 * (double)free_b), ctx->ws_budget);
+  int64_t cap = std::max<int64_t>(budget / bpe, 1 << 16);
+  cap = std::min(cap, cap_all);
+  ws.chunks.assign(1, 0);
+  if (cap >= cap_all || nl.entry_prefix.size() != (size_t)n_atoms + 1) {
+    ws.chunks.push_back(n_atoms);
+    cap = cap_all;
+  } else {
+    const double margin = (double)cap_all / std::max<double>(1.0, (double)nl.n_entries);
+    int64_t a = 0;
+    while (a < n_atoms) {
+      int64_t b = a + 1;
+      while (b < n_atoms && (double)(nl.entry_prefix[b + 1] - nl.entry_prefix[a]) * margin <= (double)cap) ++b;
+      ws.chunks.push_back(b);
+      a = b;
+    }
+  }
+  ws.cap = cap = rup(cap, 128);
+  auto fbuf = [&](int64_t rows, int64_t width) -> float* {
+    ws.bufs.emplace_back(new DevBuf());
+    ws.bufs.back()->ensure((size_t)rows * width * 4);
+    return ws.bufs.back()->as<float>();
+  };
+  if (ws.chunks.size() > 2) {
+    ws.c_ei.ensure(cap * 4);
+    ws.c_ej.ensure(cap * 4);
+    ws.c_rij.ensure(cap * 16);
+    ws.c_eoff.ensure((n_atoms + 1) * 4);
+    ws.c_nedge.ensure(64);
+  }
   ws.geo = fbuf(cap, kGeo);
   ws.h0 = fbuf(cap, ws.K0p);
   ws.a_tb.clear();
@@ -698,24 +1014,56 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap, int64_t n_atoms) {
   ws.gv[0] = fbuf(cap, d.NY * d.C);
   ws.gv[1] = fbuf(cap, d.NY * d.C);
   ws.ggc = fbuf(cap, d.NY * d.C);
+  ws.ggam = fbuf(n_atoms, d.NY * d.C);
   ws.gew = fbuf(cap, 2 * d.NW);
   ws.gY = fbuf(cap, 16);
   ws.gu = fbuf(cap, 1);
-  ws.gr = reinterpret_cast<float4*>(fbuf(cap, 4));
+  ws.gr = ws.grbuf.as<float4>();
+}
+
+// Points the pipeline at chunk `c` (centres chunks[c] .. chunks[c+1]); with a
+// single chunk the views are the whole-system arrays themselves.
+void chunk_view_async(nq_ctx* ctx, int c) {
+  Workspace& ws = ctx->ws;
+  const int64_t a0 = ws.chunks[c], a1 = ws.chunks[c + 1];
+  ws.v_a0 = a0;
+  ws.v_n = a1 - a0;
+  ws.v_e0 = ws.eoff.as<int>() + a0;
+  if (ws.chunks.size() == 2) {
+    ws.v_nedge = ws.nedge.as<int>();
+    ws.v_ei = ws.ei.as<int>();
+    ws.v_ej = ws.ej.as<int>();
+    ws.v_rij = ws.rij.as<float4>();
+    ws.v_eoff = ws.eoff.as<int>();
+    return;
+  }
+  const int sp = span_begin(ctx, "chunk_view");
+  k_chunk_edges<<<grid_for(ws.cap, 256), 256, 0, ctx->stream>>>(
+      ws.eoff.as<int>(), a0, a1, ws.cap, ws.ei.as<int>(), ws.ej.as<int>(), ws.rij.as<float4>(), ws.c_ei.as<int>(),
+      ws.c_ej.as<int>(), ws.c_rij.as<float4>(), ws.c_nedge.as<int>(), ctx->nl.flags.as<int>());
+  k_chunk_offsets<<<grid_for(a1 - a0 + 1, 256), 256, 0, ctx->stream>>>(ws.eoff.as<int>(), a0, a1,
+                                                                       ws.c_eoff.as<int>());
+  NQ_HIP(hipGetLastError());
+  span_end(ctx, sp);
+  ws.v_nedge = ws.c_nedge.as<int>();
+  ws.v_ei = ws.c_ei.as<int>();
+  ws.v_ej = ws.c_ej.as<int>();
+  ws.v_rij = ws.c_rij.as<float4>();
+  ws.v_eoff = ws.c_eoff.as<int>();
 }
 
 // ------------------------------------------------------------------ forward
-void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64_t n, double* energy,
-                   double* atom_energy) {
+void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy) {
   const Dims& d = m->dims;
   Workspace& ws = ctx->ws;
+  const int64_t n = ws.v_n;
   hipStream_t s = ctx->stream;
-  const int* ne = ws.nedge.as<int>();
+  const int* ne = ws.v_nedge;
   const int64_t cap = ws.cap;
   const float* u = ws.geo + 1;
   {
     const int sp_ = span_begin(ctx, "geometry");
-    k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.rij.as<float4>(), ws.ei.as<int>(), ws.ej.as<int>(),
+    k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.v_rij, ws.v_ei, ws.v_ej, ws.v_a0,
                                                         species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
                                                    ctx->nl.flags.as<int>());
     span_end(ctx, sp_);
@@ -746,35 +1094,18 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64
     if (d.L == 1)
       {
         const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
-        k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+        k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
                                                           ws.gam[t]);
         span_end(ctx, sp_);
       }
     else
       {
         const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
-        k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), esrc, lde, ws.geo, d.C, inv_sqrt_nu,
+        k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
                                                           ws.gam[t]);
         span_end(ctx, sp_);
       }
-    const int epb = 256 / d.C;
-    const float* mix = last ? nullptr : m->mix.as<float>() + m->mix_off[t - 1];
-    if (d.L == 1)
-      {
-        const int sp_ = span_begin(ctx, "tp_fwd" + std::to_string(t));
-        k_tp_fwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
-                                                             ws.s[t], d.nscal * d.C, mix, ws.V[t]);
-        span_end(ctx, sp_);
-      }
-    else
-      {
-        const int sp_ = span_begin(ctx, "tp_fwd" + std::to_string(t));
-        k_tp_fwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(),
-                                                             ws.s[t], d.nscal * d.C, mix, ws.V[t]);
-        span_end(ctx, sp_);
-      }
+    launch_tp_fwd(ctx, m, t);
     NQ_HIP(hipGetLastError());
     // latent MLP on [x | s]; the last layer applies the residual update
     for (int k = 0; k < d.n_lat; ++k) {
@@ -807,23 +1138,19 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, int64
   }
   {
     const int sp_ = span_begin(ctx, "atom_energy");
-    k_atom_energy<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.eij, ws.atomE, atom_energy);
-    span_end(ctx, sp_);
-  }
-  {
-    const int sp_ = span_begin(ctx, "total_energy");
-    k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+    k_atom_energy<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.v_eoff, ws.eij, ws.atomE + ws.v_a0,
+                                                   atom_energy ? atom_energy + ws.v_a0 : nullptr);
     span_end(ctx, sp_);
   }
   NQ_HIP(hipGetLastError());
 }
 
 // ------------------------------------------------------------------ adjoint
-void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
+void backward_async(nq_ctx* ctx, const nq_model* m) {
   const Dims& d = m->dims;
   Workspace& ws = ctx->ws;
   hipStream_t s = ctx->stream;
-  const int* ne = ws.nedge.as<int>();
+  const int* ne = ws.v_nedge;
   const int64_t cap = ws.cap;
   const float* u = ws.geo + 1;
   {
@@ -874,47 +1201,10 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
       gemm(ctx, m, *m->lat[t - 1][k], true, ld, ep, "bwd.latent" + std::to_string(t) + "." + std::to_string(k));
       gout = ws.gh[k % 2];
     }
-    // tensor-product adjoint
-    const int epb = 256 / d.C;
-    const float* mix = last ? nullptr : m->mix.as<float>() + m->mix_off[t - 1];
-    const float* gvin = last ? nullptr : ws.gv[gvcur];
-    float* gvout = ws.gv[1 - gvcur];
-    if (d.L == 1)
-      {
-        const int sp_ = span_begin(ctx, "tp_bwd" + std::to_string(t));
-        k_tp_bwd<1><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
-                                                             d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
-                                                             ws.gY);
-        span_end(ctx, sp_);
-      }
-    else
-      {
-        const int sp_ = span_begin(ctx, "tp_bwd" + std::to_string(t));
-        k_tp_bwd<2><<<grid_for(cap, epb), 256, 0, s>>>(ne, ws.ei.as<int>(), ws.geo, d.C, t == 1, last, ws.we1,
-                                                             2 * d.NW, ws.V[t - 1], ws.gam[t], m->cg.as<float>(), ws.gs,
-                                                             d.nscal * d.C, gvin, mix, ws.ggc, gvout, ws.gew, 2 * d.NW,
-                                                             ws.gY);
-        span_end(ctx, sp_);
-      }
+    // tensor-product adjoint, then the environment-sum adjoint -> gew[:, NW:2NW], gY
+    launch_tp_bwd(ctx, m, t, ws.gv[gvcur], ws.gv[1 - gvcur]);
     gvcur = 1 - gvcur;
-    // environment-sum adjoint -> gew[:, NW:2NW], gY
-    const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
-    const int lde = t == 1 ? 2 * d.NW : d.NW;
-    if (d.L == 1)
-      {
-        const int sp_ = span_begin(ctx, "env_bwd" + std::to_string(t));
-        k_env_bwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
-                                                          inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
-        span_end(ctx, sp_);
-      }
-    else
-      {
-        const int sp_ = span_begin(ctx, "env_bwd" + std::to_string(t));
-        k_env_bwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.ggc, esrc, lde, ws.geo, d.C,
-                                                          inv_sqrt_nu, ws.gew, 2 * d.NW, d.NW, ws.gY);
-        span_end(ctx, sp_);
-      }
+    launch_env_bwd(ctx, m, t);
     NQ_HIP(hipGetLastError());
     if (t > 1)
       gemm(ctx, m, *m->env[t - 1], true, a_plain(ws.gew + d.NW, 2 * d.NW, d.NW), e_add(ws.gx, d.D, d.D),
@@ -940,14 +1230,24 @@ void backward_async(nq_ctx* ctx, const nq_model* m, int64_t n, double* forces) {
   {
     const int sp_ = span_begin(ctx, "geometry_bwd");
     k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
-                                                            d.p, (float)d.rc, d.NY, ws.gr);
+                                                            d.p, (float)d.rc, d.NY, ws.v_e0, ws.gr);
     span_end(ctx, sp_);
   }
-  {
-    const int sp_ = span_begin(ctx, "forces");
-    k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ne, ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr, forces);
-    span_end(ctx, sp_);
-  }
+  NQ_HIP(hipGetLastError());
+}
+
+// Whole-system totals after every chunk: compensated energy and force gather.
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces) {
+  Workspace& ws = ctx->ws;
+  hipStream_t s = ctx->stream;
+  const int64_t n = ws.n_atoms;
+  int sp = span_begin(ctx, "total_energy");
+  k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+  span_end(ctx, sp);
+  sp = span_begin(ctx, "forces");
+  k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ws.nedge.as<int>(), ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr,
+                                            forces);
+  span_end(ctx, sp);
   NQ_HIP(hipGetLastError());
 }
 

@@ -108,6 +108,10 @@ class Potential:
                                  pos.shape[0], _cell(box), float(dt_fs), int(n_steps), _ptr(forces),
                                  _ptr(epot), _ptr(ekin)), self._ctx)
 
+    def set_workspace_budget(self, nbytes: int):
+        """Cap the per-edge activation memory; larger systems run in chunks of centres."""
+        B.check(self.lib.nq_ctx_set_workspace_budget(self._ctx, int(nbytes)), self._ctx)
+
     def stats(self):
         ne, nr = C.c_int64(0), C.c_int64(0)
         B.check(self.lib.nq_stats(self._ctx, C.byref(ne), C.byref(nr)), self._ctx)
