@@ -190,6 +190,7 @@ def main():
     ap.add_argument("--compare", default="fp32,bf16", help="other precision modes timed alongside")
     ap.add_argument("--cpu-sample-atoms", type=int, default=6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-autotune", action="store_true", help="skip the tile-shape autotuner")
     ap.add_argument("--md", type=int, default=0, metavar="STEPS",
                     help="instead: NVE velocity-Verlet run of STEPS steps (dt 0.5 fs, 300 K) through nq_step")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
@@ -230,8 +231,13 @@ def main():
 
     results = {}
     modes = [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision]
+    tuned = {}
     for mode in modes:
         pot = Potential(cf.model, w, mode)
+        if not args.no_autotune:
+            rep = pot.autotune(P, Z, box, reps=2)
+            tuned[mode] = {s["name"]: s["chosen"] for s in rep["sites"]}
+            log(f"{mode}: autotuned tile shapes {tuned[mode]}")
         steps = args.steps if mode == args.precision else max(3, min(args.steps, 10))
         dt, report, ne, E, F = timed_run(pot, P, Z, box, steps, args.warmup if mode == args.precision else 2)
         _, _, Ei = pot.energy_forces(P, Z, box, atom_energy=True)
@@ -278,6 +284,8 @@ def main():
         for mode, r in results.items():
             modes_out[mode].update(errors(smp, r["F"], r["Ei"]))
     line["modes"] = modes_out
+    if tuned:
+        line["autotune"] = tuned.get(args.precision)
     line["kernels_top"] = sorted(
         [{"name": k["name"], "ms_per_step": k["ms_total"] / main_res["steps"], "launches": k["count"]}
          for k in main_res["report"]["kernels"]], key=lambda k: -k["ms_per_step"])

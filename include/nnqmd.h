@@ -150,6 +150,19 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
  * results do not depend on the chunking. Synchronises the stream. */
 nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes);
 
+/* Autotuner of the matrix-core products: for every per-edge MLP product of
+ * one nq_energy_forces evaluation on this system, times each tile-shape
+ * candidate (rows per workgroup and wave grid) over `reps` evaluations with HIP
+ * events on the context's stream, and keeps the fastest for `model` (later
+ * calls use it). Positions/species/cell as in nq_energy_forces. If report is
+ * not NULL, a JSON object {"sites": [{"name", "np", "chosen", "ms": [...]}]} is
+ * written to report[cap] (host); *len (host, may be NULL) receives its length.
+ * Results of the energy/force evaluation do not depend on the choice.
+ * Synchronises the stream. */
+nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int32_t* species,
+                      int64_t n, const double cell[3], int32_t reps, char* report, int64_t cap,
+                      int64_t* len);
+
 /* Per-kernel timing. While enabled, every kernel launch of nq_energy_forces
  * (not of nq_step's graph) is bracketed by HIP events recorded on the
  * context's stream. nq_timing_report synchronises the stream and writes a JSON

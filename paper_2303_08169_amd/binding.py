@@ -19,7 +19,7 @@ PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 EXPORTS = ["nq_ctx_create", "nq_ctx_set_stream", "nq_ctx_destroy", "nq_model_weight_layout",
            "nq_model_create", "nq_model_destroy", "nq_neighbor_build", "nq_energy_forces", "nq_step",
-           "nq_stats", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_timing",
+           "nq_stats", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_autotune", "nq_timing",
            "nq_timing_report",
            "nq_status_str", "nq_last_error"]
 
@@ -87,6 +87,7 @@ def lib():
         "nq_edges_export": (C.c_int, [vp, vp, vp, i64, P(i64)]),
         "nq_debug_export": (C.c_int, [vp, vp, C.c_char_p, vp, i64, P(i64), P(i64)]),
         "nq_ctx_set_workspace_budget": (C.c_int, [vp, i64]),
+        "nq_autotune": (C.c_int, [vp, vp, vp, vp, i64, P(dbl), i32, C.c_char_p, i64, P(i64)]),
         "nq_timing": (C.c_int, [vp, C.c_int]),
         "nq_timing_report": (C.c_int, [vp, C.c_char_p, i64, P(i64)]),
         "nq_status_str": (C.c_char_p, [C.c_int]),

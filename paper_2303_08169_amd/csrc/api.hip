@@ -438,6 +438,74 @@ nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes) {
   });
 }
 
+nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int32_t* species, int64_t n,
+                      const double cell[3], int32_t reps, char* report, int64_t cap, int64_t* len) {
+  return guarded(ctx, [&] {
+    check_common(ctx, model, pos, species, n, cell);
+    NQ_REQUIRE(reps >= 1 && reps <= 100, NQ_ERR_ARG, "reps must be 1..100");
+    NQ_HIP(hipSetDevice(ctx->device));
+    ensure_list(ctx, model, pos, n, cell);
+    DevBuf scratch;
+    scratch.ensure((size_t)(n * 3 + 8) * sizeof(double));
+    double* F = scratch.as<double>();
+    double* E = F + n * 3;
+    const bool was_timing = ctx->timing;
+    std::map<std::string, std::vector<double>> ms;  // site -> mean ms per variant
+    int nvar = 1;
+    for (const auto& kv : ctx->site_np) nvar = std::max(nvar, gemm_variant_count(model->dims.prec, kv.second));
+    nvar = std::max(nvar, 4);
+    try {
+      for (int v = 0; v < nvar; ++v) {
+        ctx->force_variant = v;
+        ctx->timing = false;
+        evaluate_async(ctx, model, pos, species, n, E, F, nullptr);  // warm-up
+        ctx->timing = true;
+        ctx->spans.clear();
+        for (int r = 0; r < reps; ++r) evaluate_async(ctx, model, pos, species, n, E, F, nullptr);
+        NQ_HIP(hipStreamSynchronize(ctx->stream));
+        std::map<std::string, double> tot;
+        for (const Span& sp : ctx->spans) {
+          float t = 0.f;
+          NQ_HIP(hipEventElapsedTime(&t, sp.a, sp.b));
+          tot[sp.name] += t;
+          ctx->event_pool.push_back(sp.a);
+          ctx->event_pool.push_back(sp.b);
+        }
+        ctx->spans.clear();
+        for (const auto& kv : ctx->site_np) ms[kv.first].push_back(tot[kv.first] / reps);
+      }
+    } catch (...) {
+      ctx->force_variant = -1;
+      ctx->timing = was_timing;
+      throw;
+    }
+    ctx->force_variant = -1;
+    ctx->timing = was_timing;
+    std::string out = "{\"sites\": [";
+    bool first = true;
+    for (const auto& kv : ms) {
+      const int np = ctx->site_np[kv.first];
+      const int nv = gemm_variant_count(model->dims.prec, np);
+      int best = 0;
+      for (int v = 1; v < nv && v < (int)kv.second.size(); ++v)
+        if (kv.second[v] < kv.second[best]) best = v;
+      model->gemm_choice[kv.first] = best;
+      out += std::string(first ? "" : ", ") + "{\"name\": \"" + kv.first + "\", \"np\": " + std::to_string(np) +
+             ", \"chosen\": " + std::to_string(best) + ", \"ms\": [";
+      for (int v = 0; v < nv && v < (int)kv.second.size(); ++v)
+        out += (v ? ", " : "") + std::to_string(kv.second[v]);
+      out += "]}";
+      first = false;
+    }
+    out += "]}";
+    if (len) *len = (int64_t)out.size();
+    if (report) {
+      NQ_REQUIRE(cap > (int64_t)out.size(), NQ_ERR_CAPACITY, "report buffer too small");
+      std::memcpy(report, out.c_str(), out.size() + 1);
+    }
+  });
+}
+
 nq_status nq_timing(nq_ctx* ctx, int enable) {
   return guarded(ctx, [&] {
     NQ_REQUIRE(ctx, NQ_ERR_ARG, "null ctx");

@@ -215,11 +215,17 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
       const int idx = tid + 256 * q;
       if (idx < A4) {
         const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
-        AT* d = &As[rr * LDA + kk];
-        d[0] = (AT)ra[q].x;
-        d[1] = (AT)ra[q].y;
-        d[2] = (AT)ra[q].z;
-        d[3] = (AT)ra[q].w;
+        if constexpr (sizeof(AT) == 4) {  // one 16-byte LDS store per float4
+          *reinterpret_cast<float4*>(&As[rr * LDA + kk]) = ra[q];
+        } else {                          // four BF16 in one 8-byte store
+          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+          bf16x4 v;
+          v[0] = (bf16)ra[q].x;
+          v[1] = (bf16)ra[q].y;
+          v[2] = (bf16)ra[q].z;
+          v[3] = (bf16)ra[q].w;
+          *reinterpret_cast<bf16x4*>(&As[rr * LDA + kk]) = v;
+        }
       }
     }
 #pragma unroll

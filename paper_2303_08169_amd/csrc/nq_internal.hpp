@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <map>
 #include <memory>
 #include <string>
 #include <vector>
@@ -114,6 +115,7 @@ struct nq_model {
   nq::DevBuf wout;                          // [edge_last] f32 final edge weights
   std::vector<nq::MixW*> mixw;              // per layer t < T (index t-1)
   std::vector<double> tp_flop_fwd, tp_flop_bwd;  // algorithmic FLOPs per edge of each layer's tensor product
+  mutable std::map<std::string, int> gemm_choice;  // tuned tile shape per matrix-core product
   ~nq_model();
 };
 
@@ -191,6 +193,8 @@ struct nq_ctx {
   int64_t ws_budget = (int64_t)160 << 30;  // bytes allowed for per-edge activations
   // per-launch timing with HIP events on the context's stream
   bool timing = false;
+  int force_variant = -1;               // >= 0 while the autotuner times one tile shape
+  std::map<std::string, int> site_np;   // output width of each named matrix-core product
   std::vector<nq::Span> spans;
   std::vector<hipEvent_t> event_pool;
 };
@@ -215,6 +219,8 @@ void chunk_view_async(nq_ctx* ctx, int chunk);
 void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy);
 void backward_async(nq_ctx* ctx, const nq_model* m);
 void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces);
+
+int gemm_variant_count(int prec, int NP);
 
 // ---- MD (md.hip)
 void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass,

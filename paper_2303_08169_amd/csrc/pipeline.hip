@@ -233,6 +233,20 @@ __device__ inline bf16x8 to_bf16x8(const float* v) {
   return r;
 }
 
+// Dynamic LDS of the tensor-product kernels (the staged mixing weights).
+extern __shared__ __attribute__((aligned(16))) float nq_dyn_lds[];
+
+// Copies the mixing weights a kernel reads (natural for the adjoint, transposed
+// for the forward; FP32 or BF16 hi | lo) into LDS and returns pointers into it.
+template <int KIND>
+__device__ inline void stage_mix(const MixPtrs& W, bool natural) {
+  const float4* src = KIND == G_F32 ? reinterpret_cast<const float4*>(natural ? W.fN : W.fT)
+                                    : reinterpret_cast<const float4*>(natural ? W.bN : W.bT);  // hi | lo
+  float4* dst = reinterpret_cast<float4*>(nq_dyn_lds);
+  for (int64_t k = threadIdx.x; k < W.n / 4; k += blockDim.x) dst[k] = src[k];
+  __syncthreads();
+}
+
 // One 16x16 output tile of a small product on the matrix cores, accumulating
 // over K: A(r, k) comes from `afetch(k)` (this lane's row, 1 or 8 values from
 // LDS), B(k, n) from `bptr(k)` (this lane's column, contiguous in k, global).
@@ -279,7 +293,7 @@ __device__ inline floatx4 tile_mma(int K, int lane, int64_t lo_off, bool bvalid,
 // Forward channel mixing of one edge group on the matrix cores. For each l3:
 // rows (edge, m), K = (path p, channel c), columns c':
 // V_t[e][l3 m][c'] = sum_{p, c} T[e][toff(p) + m][c] W_l3[(p, c)][c'].
-template <int KIND, int LMAX>
+template <int KIND, int LMAX, bool WL>
 __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int64_t ne, const MixPtrs& W,
                                float* __restrict__ vout) {
   constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
@@ -299,12 +313,18 @@ __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int6
         const int n = ct * 16 + (lane & 15);
         auto af = [&](int k, float* v) {
           if (!rv) return;
-          const float* src = Tl + (el * NT + pi.toff[l3][k / C] + m) * C + (k % C);
+          const float* src = Tl + (el * NT + pi.toff[l3][k / C] + m) * (C + 4) + (k % C);
           if constexpr (KIND == G_F32) v[0] = *src; else load8(src, v);
         };
         auto bp = [&](int k) -> const void* {
-          if constexpr (KIND == G_F32) return W.fT + woff + (int64_t)n * K + k;
-          else return W.bT + woff + (int64_t)n * K + k;
+          const int64_t o = woff + (int64_t)n * K + k;
+          if constexpr (WL) {
+            if constexpr (KIND == G_F32) return nq_dyn_lds + o;
+            else return reinterpret_cast<const bf16*>(nq_dyn_lds) + o;
+          } else {
+            if constexpr (KIND == G_F32) return W.fT + o;
+            else return W.bT + o;
+          }
         };
         const floatx4 acc = tile_mma<KIND>(K, lane, W.n, n < C, af, bp);
 #pragma unroll
@@ -321,7 +341,7 @@ __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int6
 
 // Adjoint of the channel mixing for one edge group, into LDS:
 // gT[e][toff(p) + m][c] = sum_{c'} gV[e][l3 m][c'] W_l3[(p, c)][c'].
-template <int KIND, int LMAX>
+template <int KIND, int LMAX, bool WL>
 __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, const MixPtrs& W) {
   constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
   const PathInfo& pi = Paths<LMAX>::pi;
@@ -340,19 +360,25 @@ __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, con
         const int n = ct * 16 + (lane & 15);
         auto af = [&](int k, float* v) {
           if (!rv) return;
-          const float* src = gVl + (el * NY + l3 * l3 + m) * C + k;
+          const float* src = gVl + (el * NY + l3 * l3 + m) * (C + 4) + k;
           if constexpr (KIND == G_F32) v[0] = *src; else load8(src, v);
         };
         auto bp = [&](int k) -> const void* {
-          if constexpr (KIND == G_F32) return W.fN + woff + (int64_t)n * C + k;
-          else return W.bN + woff + (int64_t)n * C + k;
+          const int64_t o = woff + (int64_t)n * C + k;
+          if constexpr (WL) {
+            if constexpr (KIND == G_F32) return nq_dyn_lds + o;
+            else return reinterpret_cast<const bf16*>(nq_dyn_lds) + o;
+          } else {
+            if constexpr (KIND == G_F32) return W.fN + o;
+            else return W.bN + o;
+          }
         };
         const floatx4 acc = tile_mma<KIND>(C, lane, W.n, n < N, af, bp);
         const int p = n / C, c = n % C;
 #pragma unroll
         for (int q = 0; q < 4; ++q) {
           const int rr = rt * 16 + 4 * (lane >> 4) + q;
-          if (rr < R && n < N) gTl[((rr / nm) * NT + pi.toff[l3][p] + rr % nm) * C + c] = acc[q];
+          if (rr < R && n < N) gTl[((rr / nm) * NT + pi.toff[l3][p] + rr % nm) * (C + 4) + c] = acc[q];
         }
       }
   }
@@ -363,18 +389,19 @@ __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, con
 // channels; one thread computes all coupling paths of one (edge, channel) in
 // registers (zero coefficients skipped at compile time), the group's T is
 // staged in LDS and mixed across channels on the matrix cores.
-template <int KIND, int LMAX>
-__global__ __launch_bounds__(256) void k_tp_fwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
+template <int KIND, int LMAX, bool WL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_fwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
                                                 const float* __restrict__ geo, int C, int first, int last,
                                                 const float* __restrict__ we1, int ldwe,
                                                 const float* __restrict__ vprev, const float* __restrict__ gam,
                                                 float* __restrict__ s, int lds, MixPtrs W, float* __restrict__ vout) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ __attribute__((aligned(16))) float Tl[256 * NT];
-  const int epb = 256 / C;
+  __shared__ __attribute__((aligned(16))) float Tl[(256 + 32) * NT];
+  const int epb = 256 / C, CP = C + 4;  // padded channel stride: rows start on different LDS banks
   const int el = threadIdx.x / C, c = threadIdx.x % C;
   const int64_t ne = *nedge_p;
   const int64_t ngroups = (ne + epb - 1) / epb;
+  if (WL && !last) stage_mix<KIND>(W, false);
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
@@ -406,9 +433,9 @@ __global__ __launch_bounds__(256) void k_tp_fwd(const int* __restrict__ nedge_p,
     }
     if (last) continue;
 #pragma unroll
-    for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * C + c] = T[k];
+    for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * CP + c] = T[k];
     __syncthreads();
-    mix_fwd<KIND, LMAX>(Tl, epb, C, grp * epb, ne, W, vout);
+    mix_fwd<KIND, LMAX, WL>(Tl, epb, C, grp * epb, ne, W, vout);
     __syncthreads();
   }
 }
@@ -492,8 +519,8 @@ __global__ __launch_bounds__(256) void k_rowdot_gu(const int* __restrict__ nedge
 // on the matrix cores through LDS). Writes the per-edge contributions
 // ggc[e][lm][c] to dE/dGamma_i, and either dE/dV_{t-1} (t > 1) or, for t = 1,
 // dE/dw0 into gew[:, 0:NW] and the w0 part of dE/dY into gY.
-template <int KIND, int LMAX>
-__global__ __launch_bounds__(256) void k_tp_bwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
+template <int KIND, int LMAX, bool WL>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_bwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
                                                 const float* __restrict__ geo, int C, int first, int last,
                                                 const float* __restrict__ we1, int ldwe,
                                                 const float* __restrict__ vprev, const float* __restrict__ gam,
@@ -502,20 +529,21 @@ __global__ __launch_bounds__(256) void k_tp_bwd(const int* __restrict__ nedge_p,
                                                 float* __restrict__ ggc, float* __restrict__ gvout,
                                                 float* __restrict__ gew, int ldgew, float* __restrict__ gY) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ __attribute__((aligned(16))) float gVl[256 * NY];
-  __shared__ __attribute__((aligned(16))) float gTl[256 * NT];
-  const int epb = 256 / C;
+  __shared__ __attribute__((aligned(16))) float gVl[(256 + 32) * NY];
+  __shared__ __attribute__((aligned(16))) float gTl[(256 + 32) * NT];
+  const int epb = 256 / C, CP = C + 4;  // padded channel stride
   const int el = threadIdx.x / C, c = threadIdx.x % C;
   const int64_t ne = *nedge_p;
   const int64_t ngroups = (ne + epb - 1) / epb;
+  if (WL && !last) stage_mix<KIND>(W, true);
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
     if (!last) {
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * C + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
+      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
       __syncthreads();
-      mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, W);
+      mix_bwd<KIND, LMAX, WL>(gVl, gTl, epb, C, W);
       __syncthreads();
     }
     if (valid) {
@@ -526,7 +554,7 @@ __global__ __launch_bounds__(256) void k_tp_bwd(const int* __restrict__ nedge_p,
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
 #pragma unroll
-      for (int k = 0; k < NT; ++k) gT[k] = last ? 0.f : gTl[(el * NT + k) * C + c];
+      for (int k = 0; k < NT; ++k) gT[k] = last ? 0.f : gTl[(el * NT + k) * CP + c];
       for_paths<LMAX>(last, [&](int, int, int l3, int toff, int qs, int) {
         if (l3 == 0) gT[toff] += gs[e * ldgs + qs * C + c];
       });
@@ -711,39 +739,75 @@ void launch_gemm_t(hipStream_t s, int64_t cap, int Kp, const void* Bt, const int
                                                                        ep);
 }
 
-// Tile shapes per output width; the split-BF16 kind keeps both weight halves
-// in LDS, so its wide shapes use fewer rows per workgroup.
-template <int KIND>
-void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, const int* nrows, const ALoad& ld,
-                    const Epi& ep) {
-  constexpr bool X3 = KIND == G_BF16X3;
+// Tile-shape candidates per output width NP: (rows per workgroup BM, wave grid
+// WM x WN). Variant 0 is the default; the autotuner (nq_autotune) times all of
+// them on the real shapes and keeps the fastest per product. Shapes whose LDS
+// (A and B tiles) would not fit are left out for the split-BF16 kind, which
+// keeps both weight halves in LDS.
+int gemm_variants(int kind, int NP) {
+  const bool x3 = kind == G_BF16X3;
   switch (NP) {
-    case 16: launch_gemm_t<KIND, 128, 16, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 32: launch_gemm_t<KIND, 128, 32, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 48: launch_gemm_t<KIND, 128, 48, 4, 1>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 64: launch_gemm_t<KIND, 128, 64, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 96: launch_gemm_t<KIND, 128, 96, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 128: launch_gemm_t<KIND, 128, 128, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 192: launch_gemm_t<KIND, 64, 192, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 256: launch_gemm_t<KIND, 64, 256, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 352: launch_gemm_t<KIND, X3 ? 32 : 64, 352, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep); break;
-    case 384:
-      if constexpr (X3) launch_gemm_t<KIND, 32, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-      else launch_gemm_t<KIND, 64, 384, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-      break;
-    case 512:
-      if constexpr (X3) launch_gemm_t<KIND, 32, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-      else launch_gemm_t<KIND, 64, 512, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-      break;
-    case 704:
-      if constexpr (X3) launch_gemm_t<KIND, 32, 704, 2, 2>(s, cap, Kp, Bt, nrows, ld, ep);
-      else launch_gemm_t<KIND, 64, 704, 1, 4>(s, cap, Kp, Bt, nrows, ld, ep);
-      break;
-    default: throw Error{NQ_ERR_UNSUPPORTED, "no matrix-core kernel for output width " + std::to_string(NP)};
+    case 16: case 32: return 3;
+    case 48: return 2;
+    case 64: case 96: case 128: case 192: case 256: return 4;
+    case 352: return x3 ? 2 : 3;
+    default: return 1;
   }
 }
 
-// y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map.
+template <int KIND>
+void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, const int* nrows, const ALoad& ld,
+                    const Epi& ep, int v) {
+  constexpr bool X3 = KIND == G_BF16X3;
+  v = v % gemm_variants(KIND, NP);
+#define NQ_G(BM, N, WM, WN) launch_gemm_t<KIND, BM, N, WM, WN>(s, cap, Kp, Bt, nrows, ld, ep)
+  switch (NP) {
+    case 16: if (v == 0) NQ_G(128, 16, 4, 1); else if (v == 1) NQ_G(64, 16, 4, 1); else NQ_G(256, 16, 4, 1); break;
+    case 32: if (v == 0) NQ_G(128, 32, 4, 1); else if (v == 1) NQ_G(64, 32, 4, 1); else NQ_G(256, 32, 4, 1); break;
+    case 48: if (v == 0) NQ_G(128, 48, 4, 1); else NQ_G(64, 48, 4, 1); break;
+    case 64:
+      if (v == 0) NQ_G(128, 64, 2, 2); else if (v == 1) NQ_G(64, 64, 2, 2);
+      else if (v == 2) NQ_G(256, 64, 2, 2); else NQ_G(128, 64, 4, 1);
+      break;
+    case 96:
+      if (v == 0) NQ_G(128, 96, 2, 2); else if (v == 1) NQ_G(64, 96, 2, 2);
+      else if (v == 2) NQ_G(256, 96, 4, 1); else NQ_G(128, 96, 4, 1);
+      break;
+    case 128:
+      if (v == 0) NQ_G(128, 128, 2, 2); else if (v == 1) NQ_G(64, 128, 2, 2);
+      else if (v == 2) NQ_G(256, 128, 4, 1); else NQ_G(128, 128, 4, 1);
+      break;
+    case 192:
+      if (v == 0) NQ_G(64, 192, 2, 2); else if (v == 1) NQ_G(32, 192, 2, 2);
+      else if (v == 2) NQ_G(128, 192, 2, 2); else NQ_G(64, 192, 4, 1);
+      break;
+    case 256:
+      if (v == 0) NQ_G(64, 256, 2, 2); else if (v == 1) NQ_G(32, 256, 2, 2);
+      else if (v == 2) NQ_G(128, 256, 2, 2); else NQ_G(64, 256, 4, 1);
+      break;
+    case 352:
+      if constexpr (X3) {
+        if (v == 0) NQ_G(32, 352, 2, 2); else NQ_G(64, 352, 2, 2);
+      } else {
+        if (v == 0) NQ_G(64, 352, 2, 2); else if (v == 1) NQ_G(32, 352, 2, 2); else NQ_G(128, 352, 2, 2);
+      }
+      break;
+    case 384:
+      if constexpr (X3) NQ_G(32, 384, 2, 2); else NQ_G(64, 384, 2, 2);
+      break;
+    case 512:
+      if constexpr (X3) NQ_G(32, 512, 2, 2); else NQ_G(64, 512, 2, 2);
+      break;
+    case 704:
+      if constexpr (X3) NQ_G(32, 704, 2, 2); else NQ_G(64, 704, 1, 4);
+      break;
+    default: throw Error{NQ_ERR_UNSUPPORTED, "no matrix-core kernel for output width " + std::to_string(NP)};
+  }
+#undef NQ_G
+}
+
+// y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map. The tile shape
+// is the model's tuned choice for this product (or the one being timed).
 void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep,
           const std::string& name) {
   const Workspace& ws = ctx->ws;
@@ -751,19 +815,35 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
   const int NP = bwd ? L.np_b : L.np_f;
   const int Kp = bwd ? L.kp_b : L.kp_f;
   const int* nr = ws.v_nedge;
+  int v = 0;
+  if (ctx->force_variant >= 0) {
+    v = ctx->force_variant;
+  } else {
+    auto it = m->gemm_choice.find(name);
+    if (it != m->gemm_choice.end()) v = it->second;
+  }
+  ctx->site_np[name] = NP;
   switch (m->dims.prec) {
     case NQ_PRECISION_BF16:
-      launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep);
+      launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep, v);
       break;
     case NQ_PRECISION_BF16X3:
-      launch_gemm_np<G_BF16X3>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep);
+      launch_gemm_np<G_BF16X3>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep, v);
       break;
     default:
-      launch_gemm_np<G_F32>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).p, nr, ld, ep);
+      launch_gemm_np<G_F32>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).p, nr, ld, ep, v);
   }
   NQ_HIP(hipGetLastError());
   span_end(ctx, sp);
 }
+
+}  // namespace
+
+int gemm_variant_count(int prec, int NP) {
+  return gemm_variants(prec == NQ_PRECISION_BF16X3 ? G_BF16X3 : (prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32), NP);
+}
+
+namespace {
 
 ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
 ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
@@ -804,8 +884,17 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
   const MixPtrs W = layer_mix(m, t);
   const unsigned grid = tp_grid(ws, d.C);
   const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1]);
+  // Staging the mixing weights in LDS halves the workgroups per CU and was
+  // measured slower than reading them through L1/L2, so it stays off.
+  const size_t wl_bytes = (size_t)W.n * 4;  // FP32 copy or BF16 hi | lo halves
+  const bool wl = false;
 #define NQ_TPF(K, LM)                                                                                    \
-  k_tp_fwd<K, LM><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, \
+  if (wl)                                                                                                \
+    k_tp_fwd<K, LM, true><<<grid, 256, wl_bytes, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
+                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.s[t],  \
+                                                  d.nscal * d.C, W, ws.V[t]);                               \
+  else                                                                                                   \
+  k_tp_fwd<K, LM, false><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, \
                                                   last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.s[t],  \
                                                   d.nscal * d.C, W, ws.V[t])
   switch (d.prec * 2 + (d.L == 2)) {
@@ -828,8 +917,16 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const MixPtrs W = layer_mix(m, t);
   const unsigned grid = tp_grid(ws, d.C);
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1]);
+  const size_t wl_bytes = (size_t)W.n * 4;
+  const bool wl = false;
 #define NQ_TPB(K, LM)                                                                                     \
-  k_tp_bwd<K, LM><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
+  if (wl)                                                                                                 \
+    k_tp_bwd<K, LM, true><<<grid, 256, wl_bytes, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
+                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.gs,     \
+                                                  d.nscal * d.C, last ? nullptr : gvin, W, ws.ggc, gvout,    \
+                                                  ws.gew, 2 * d.NW, ws.gY);                                  \
+  else                                                                                                    \
+  k_tp_bwd<K, LM, false><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
                                                   last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.gs,     \
                                                   d.nscal * d.C, last ? nullptr : gvin, W, ws.ggc, gvout,    \
                                                   ws.gew, 2 * d.NW, ws.gY)

@@ -108,6 +108,18 @@ class Potential:
                                  pos.shape[0], _cell(box), float(dt_fs), int(n_steps), _ptr(forces),
                                  _ptr(epot), _ptr(ekin)), self._ctx)
 
+    def autotune(self, pos, species, box, reps: int = 3):
+        """Time every tile-shape candidate of every matrix-core product on this
+        system and keep the fastest; returns the library's JSON report."""
+        import json
+        self._check_inputs(pos, species)
+        self._sync_stream()
+        buf = C.create_string_buffer(1 << 20)
+        n = C.c_int64(0)
+        B.check(self.lib.nq_autotune(self._ctx, self._model, _ptr(pos), _ptr(species), pos.shape[0], _cell(box),
+                                     int(reps), buf, len(buf), C.byref(n)), self._ctx)
+        return json.loads(buf.value.decode())
+
     def set_workspace_budget(self, nbytes: int):
         """Cap the per-edge activation memory; larger systems run in chunks of centres."""
         B.check(self.lib.nq_ctx_set_workspace_budget(self._ctx, int(nbytes)), self._ctx)

@@ -59,3 +59,20 @@ def test_big_model_sampled():
     np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-6 * np.abs(F).sum())
     assert abs(ne / len(pos) - cf.model.avg_num_neighbors) < 0.05 * cf.model.avg_num_neighbors
     pot.close()
+
+
+def test_autotune_keeps_results_bitwise():
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_1024_l2")
+    pot = Potential(cf.model, w, "bf16x3")
+    P, Z = _dev(pos, z)
+    E1, F1 = pot.energy_forces(P, Z, L)
+    torch.cuda.synchronize()
+    E1, F1 = E1.clone(), F1.clone()
+    rep = pot.autotune(P, Z, L, reps=1)
+    assert rep["sites"] and all(0 <= s["chosen"] < len(s["ms"]) for s in rep["sites"])
+    E2, F2 = pot.energy_forces(P, Z, L)
+    torch.cuda.synchronize()
+    assert E1.item() == E2.item()
+    assert torch.equal(F1, F2)
+    pot.close()
