@@ -21,6 +21,7 @@
 
 #include "cg_const.hpp"
 #include "gemm.hpp"
+#include "mix32.hpp"
 #include "nq_internal.hpp"
 
 namespace nq {
@@ -233,19 +234,9 @@ __device__ inline bf16x8 to_bf16x8(const float* v) {
   return r;
 }
 
-// Dynamic LDS of the tensor-product kernels (the staged mixing weights).
+// Dynamic LDS of the tensor-product kernels: the edge group's T (forward) or
+// gV and gT (adjoint), rows padded to C + 4 floats.
 extern __shared__ __attribute__((aligned(16))) float nq_dyn_lds[];
-
-// Copies the mixing weights a kernel reads (natural for the adjoint, transposed
-// for the forward; FP32 or BF16 hi | lo) into LDS and returns pointers into it.
-template <int KIND>
-__device__ inline void stage_mix(const MixPtrs& W, bool natural) {
-  const float4* src = KIND == G_F32 ? reinterpret_cast<const float4*>(natural ? W.fN : W.fT)
-                                    : reinterpret_cast<const float4*>(natural ? W.bN : W.bT);  // hi | lo
-  float4* dst = reinterpret_cast<float4*>(nq_dyn_lds);
-  for (int64_t k = threadIdx.x; k < W.n / 4; k += blockDim.x) dst[k] = src[k];
-  __syncthreads();
-}
 
 // One 16x16 output tile of a small product on the matrix cores, accumulating
 // over K: A(r, k) comes from `afetch(k)` (this lane's row, 1 or 8 values from
@@ -293,7 +284,7 @@ __device__ inline floatx4 tile_mma(int K, int lane, int64_t lo_off, bool bvalid,
 // Forward channel mixing of one edge group on the matrix cores. For each l3:
 // rows (edge, m), K = (path p, channel c), columns c':
 // V_t[e][l3 m][c'] = sum_{p, c} T[e][toff(p) + m][c] W_l3[(p, c)][c'].
-template <int KIND, int LMAX, bool WL>
+template <int KIND, int LMAX>
 __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int64_t ne, const MixPtrs& W,
                                float* __restrict__ vout) {
   constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
@@ -318,13 +309,8 @@ __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int6
         };
         auto bp = [&](int k) -> const void* {
           const int64_t o = woff + (int64_t)n * K + k;
-          if constexpr (WL) {
-            if constexpr (KIND == G_F32) return nq_dyn_lds + o;
-            else return reinterpret_cast<const bf16*>(nq_dyn_lds) + o;
-          } else {
-            if constexpr (KIND == G_F32) return W.fT + o;
-            else return W.bT + o;
-          }
+          if constexpr (KIND == G_F32) return W.fT + o;
+          else return W.bT + o;
         };
         const floatx4 acc = tile_mma<KIND>(K, lane, W.n, n < C, af, bp);
 #pragma unroll
@@ -341,7 +327,7 @@ __device__ inline void mix_fwd(const float* Tl, int epb, int C, int64_t e0, int6
 
 // Adjoint of the channel mixing for one edge group, into LDS:
 // gT[e][toff(p) + m][c] = sum_{c'} gV[e][l3 m][c'] W_l3[(p, c)][c'].
-template <int KIND, int LMAX, bool WL>
+template <int KIND, int LMAX>
 __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, const MixPtrs& W) {
   constexpr int NY = (LMAX + 1) * (LMAX + 1), NT = LMAX == 1 ? 8 : 35;
   const PathInfo& pi = Paths<LMAX>::pi;
@@ -365,13 +351,8 @@ __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, con
         };
         auto bp = [&](int k) -> const void* {
           const int64_t o = woff + (int64_t)n * C + k;
-          if constexpr (WL) {
-            if constexpr (KIND == G_F32) return nq_dyn_lds + o;
-            else return reinterpret_cast<const bf16*>(nq_dyn_lds) + o;
-          } else {
-            if constexpr (KIND == G_F32) return W.fN + o;
-            else return W.bN + o;
-          }
+          if constexpr (KIND == G_F32) return W.fN + o;
+          else return W.bN + o;
         };
         const floatx4 acc = tile_mma<KIND>(C, lane, W.n, n < N, af, bp);
         const int p = n / C, c = n % C;
@@ -384,59 +365,120 @@ __device__ inline void mix_bwd(const float* gVl, float* gTl, int epb, int C, con
   }
 }
 
-// Forward tensor product of one layer: s (scalar paths) and, for t < T, the
-// mixed features V_t. A workgroup loops over groups of (256 / C) edges x C
-// channels; one thread computes all coupling paths of one (edge, channel) in
-// registers (zero coefficients skipped at compile time), the group's T is
-// staged in LDS and mixed across channels on the matrix cores.
-template <int KIND, int LMAX, bool WL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_fwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
-                                                const float* __restrict__ geo, int C, int first, int last,
-                                                const float* __restrict__ we1, int ldwe,
-                                                const float* __restrict__ vprev, const float* __restrict__ gam,
-                                                float* __restrict__ s, int lds, MixPtrs W, float* __restrict__ vout) {
-  constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ __attribute__((aligned(16))) float Tl[(256 + 32) * NT];
-  const int epb = 256 / C, CP = C + 4;  // padded channel stride: rows start on different LDS banks
-  const int el = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t ne = *nedge_p;
+static_assert(Paths<2>::pi.toff[0][0] == mix32::TOFF[0][0] && Paths<2>::pi.toff[0][1] == mix32::TOFF[0][1] &&
+                  Paths<2>::pi.toff[0][2] == mix32::TOFF[0][2] && Paths<2>::pi.toff[1][0] == mix32::TOFF[1][0] &&
+                  Paths<2>::pi.toff[1][1] == mix32::TOFF[1][1] && Paths<2>::pi.toff[1][2] == mix32::TOFF[1][2] &&
+                  Paths<2>::pi.toff[1][3] == mix32::TOFF[1][3] && Paths<2>::pi.toff[2][0] == mix32::TOFF[2][0] &&
+                  Paths<2>::pi.toff[2][1] == mix32::TOFF[2][1] && Paths<2>::pi.toff[2][2] == mix32::TOFF[2][2] &&
+                  Paths<2>::pi.toff[2][3] == mix32::TOFF[2][3] && Paths<2>::pi.moff[1] == mix32::MOFF[1] &&
+                  Paths<2>::pi.moff[2] == mix32::MOFF[2] && TPSize<2>::NT == mix32::NT,
+              "path layout of the 32-channel mixing plan");
+
+// LDS bytes of one tensor-product workgroup: rows of C + 4 floats for the
+// group's (256 / C) edges x (NT, plus NY for the adjoint) components.
+inline size_t tp_lds_bytes(int C, int L, bool adjoint) {
+  const int NT = L == 1 ? 8 : 35, NY = (L + 1) * (L + 1);
+  return (size_t)(256 / C) * (C + 4) * (NT + (adjoint ? NY : 0)) * sizeof(float);
+}
+
+struct TpFwdArgs {
+  const int* nedge_p;
+  const int* ei;
+  const float* geo;
+  int C, first, last;
+  const float* we1;
+  int ldwe;
+  const float* vprev;
+  const float* gam;
+  float* s;
+  int lds;
+  MixPtrs W;
+  float* vout;
+};
+
+// T = C (V (x) Gamma_i) for one (edge, channel), path by path (zero
+// coefficients skipped at compile time): each component goes straight to the
+// edge's LDS rows Trow (stride CP), the scalar paths also to s.
+template <int LMAX>
+__device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, int c, float* Trow, int CP) {
+  constexpr int NY = TPSize<LMAX>::NY;
+  const float* Y = a.geo + e * kGeo + kGeoY;
+  float V[NY], G[NY];
+  load_vprev<NY>(a.first, e, c, a.C, a.we1, a.ldwe, a.vprev, Y, V);
+  const int64_t i = a.ei[e];
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) G[lm] = a.gam[(i * NY + lm) * a.C + c];
+  for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
+#pragma unroll
+    for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+      float acc = 0.f;
+#pragma unroll
+      for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+#pragma unroll
+        for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+          const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
+          if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * G[l2 * l2 + m2];
+        }
+      Trow[(toff + m3) * CP + c] = acc;
+      if (l3 == 0) a.s[e * a.lds + qs * a.C + c] = acc;
+    }
+  });
+}
+
+// Persistent loop of one wavefront over groups of (256 / C) edges x C
+// channels: one thread per (edge, channel) computes T, the group's T is staged
+// in LDS and mixed across channels and paths on the matrix cores. MW < 0: the
+// output tiles are dealt round-robin to the 4 waves and the weights read per
+// tile; MW = 0..3: the wave's fixed tiles of the l <= 2, 32-channel plan, with
+// their weight fragments loaded once into registers.
+template <int KIND, int LMAX, int MW>
+__device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
+  constexpr int NT = TPSize<LMAX>::NT;
+  const int C = MW >= 0 ? mix32::C : a.C;
+  const int epb = 256 / C, CP = C + 4;
+  const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
+  float* Tl = nq_dyn_lds;
+  const int64_t ne = *a.nedge_p;
   const int64_t ngroups = (ne + epb - 1) / epb;
-  if (WL && !last) stage_mix<KIND>(W, false);
+  mix32::FwdB<KIND, (MW < 0 ? 0 : MW)> B;
+  if constexpr (MW >= 0) {
+    if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fT) : a.W.bT, a.W.n, lane);
+  }
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
-    const bool valid = e < ne;
-    float T[NT];
+    float* Trow = Tl + el * NT * CP;
+    if (e < ne) {
+      tp_fwd_edge<LMAX>(a, e, c, Trow, CP);
+    } else if (!a.last) {
 #pragma unroll
-    for (int k = 0; k < NT; ++k) T[k] = 0.f;
-    if (valid) {
-      const float* Y = geo + e * kGeo + kGeoY;
-      float V[NY], G[NY];
-      load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
-      const int64_t i = ei[e];
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
-      for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int qs, int) {
-#pragma unroll
-        for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
-          float a = 0.f;
-#pragma unroll
-          for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
-#pragma unroll
-            for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
-              const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
-              if (cgv != 0.f) a += cgv * V[l1 * l1 + m1] * G[l2 * l2 + m2];
-            }
-          T[toff + m3] = a;
-        }
-        if (l3 == 0) s[e * lds + qs * C + c] = T[toff];
-      });
+      for (int k = 0; k < NT; ++k) Trow[k * CP + c] = 0.f;
     }
-    if (last) continue;
-#pragma unroll
-    for (int k = 0; k < NT; ++k) Tl[(el * NT + k) * CP + c] = T[k];
+    if (a.last) continue;
     __syncthreads();
-    mix_fwd<KIND, LMAX, WL>(Tl, epb, C, grp * epb, ne, W, vout);
+    if constexpr (MW >= 0)
+      mix32::mix_fwd<KIND, MW>(B, Tl, grp * epb, ne, a.vout, lane);
+    else
+      mix_fwd<KIND, LMAX>(Tl, epb, C, grp * epb, ne, a.W, a.vout);
     __syncthreads();
+  }
+}
+
+// Forward tensor product of one layer: s (scalar paths) and, for t < T, the
+// mixed features V_t. C32: the l <= 2, 32-channel model, each wave running its
+// own mixing plan (the wave index is uniform, every wave passes the same
+// barriers).
+template <int KIND, int LMAX, bool C32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_fwd(TpFwdArgs a) {
+  if constexpr (C32) {
+    static_assert(LMAX == 2, "the 32-channel plan is for l <= 2");
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+      case 0: tp_fwd_loop<KIND, LMAX, 0>(a); break;
+      case 1: tp_fwd_loop<KIND, LMAX, 1>(a); break;
+      case 2: tp_fwd_loop<KIND, LMAX, 2>(a); break;
+      default: tp_fwd_loop<KIND, LMAX, 3>(a); break;
+    }
+  } else {
+    tp_fwd_loop<KIND, LMAX, -1>(a);
   }
 }
 
@@ -515,95 +557,137 @@ __global__ __launch_bounds__(256) void k_rowdot_gu(const int* __restrict__ nedge
   if (valid && l == 0) gu[e] += c * acc;
 }
 
-// Adjoint of one layer's tensor product (and of the channel mixing for t < T,
-// on the matrix cores through LDS). Writes the per-edge contributions
-// ggc[e][lm][c] to dE/dGamma_i, and either dE/dV_{t-1} (t > 1) or, for t = 1,
-// dE/dw0 into gew[:, 0:NW] and the w0 part of dE/dY into gY.
-template <int KIND, int LMAX, bool WL>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_bwd(const int* __restrict__ nedge_p, const int* __restrict__ ei,
-                                                const float* __restrict__ geo, int C, int first, int last,
-                                                const float* __restrict__ we1, int ldwe,
-                                                const float* __restrict__ vprev, const float* __restrict__ gam,
-                                                const float* __restrict__ gs, int ldgs,
-                                                const float* __restrict__ gvin, MixPtrs W,
-                                                float* __restrict__ ggc, float* __restrict__ gvout,
-                                                float* __restrict__ gew, int ldgew, float* __restrict__ gY) {
+struct TpBwdArgs {
+  const int* nedge_p;
+  const int* ei;
+  const float* geo;
+  int C, first, last;
+  const float* we1;
+  int ldwe;
+  const float* vprev;
+  const float* gam;
+  const float* gs;
+  int ldgs;
+  const float* gvin;
+  MixPtrs W;
+  float* ggc;
+  float* gvout;
+  float* gew;
+  int ldgew;
+  float* gY;
+};
+
+// Adjoint of the tensor product of one (edge, channel), given dE/dT from the
+// mixing adjoint (gTrow: this edge's rows in LDS, null for the last layer) and
+// dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i, and
+// either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and the
+// w0 part of dE/dY into gY.
+template <int LMAX>
+__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP) {
+  constexpr int NY = TPSize<LMAX>::NY;
+  const int C = a.C;
+  const float* Y = a.geo + e * kGeo + kGeoY;
+  float V[NY], G[NY];
+  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, Y, V);
+  const int64_t i = a.ei[e];
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) G[lm] = a.gam[(i * NY + lm) * C + c];
+  float gV[NY], gG[NY];
+#pragma unroll
+  for (int k = 0; k < NY; ++k) {
+    gV[k] = 0.f;
+    gG[k] = 0.f;
+  }
+  for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
+#pragma unroll
+    for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
+      float g = a.last ? 0.f : gTrow[(toff + m3) * CP + c];
+      if (l3 == 0) g += a.gs[e * a.ldgs + qs * C + c];
+#pragma unroll
+      for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
+#pragma unroll
+        for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
+          const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
+          if (cgv != 0.f) {
+            const float w = cgv * g;
+            gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
+            gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
+          }
+        }
+    }
+  });
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) a.ggc[(e * NY + lm) * C + c] = gG[lm];
+  if (!a.first) {
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) a.gvout[(e * NY + lm) * C + c] = gV[lm];
+  } else {
+    // V0[c][lm] = w0[l][c] Y[lm]
+#pragma unroll
+    for (int l = 0; l <= LMAX; ++l) {
+      float gw = 0.f;
+      const float w0 = a.we1[e * a.ldwe + l * C + c];
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        gw += gV[l * l + m] * Y[l * l + m];
+        float part = w0 * gV[l * l + m];
+        for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
+        if (c == 0) a.gY[e * 16 + l * l + m] += part;
+      }
+      a.gew[e * a.ldgew + l * C + c] = gw;
+    }
+  }
+}
+
+// Persistent loop of one wavefront of the adjoint: the group's dE/dV_t is
+// staged in LDS, mixed back to dE/dT on the matrix cores (MW as in
+// tp_fwd_loop), then each thread runs the adjoint of its (edge, channel).
+template <int KIND, int LMAX, int MW>
+__device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  __shared__ __attribute__((aligned(16))) float gVl[(256 + 32) * NY];
-  __shared__ __attribute__((aligned(16))) float gTl[(256 + 32) * NT];
-  const int epb = 256 / C, CP = C + 4;  // padded channel stride
-  const int el = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t ne = *nedge_p;
+  const int C = MW >= 0 ? mix32::C : a.C;
+  const int epb = 256 / C, CP = C + 4;
+  const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
+  float* gVl = nq_dyn_lds;
+  float* gTl = nq_dyn_lds + epb * NY * CP;
+  const int64_t ne = *a.nedge_p;
   const int64_t ngroups = (ne + epb - 1) / epb;
-  if (WL && !last) stage_mix<KIND>(W, true);
+  mix32::BwdB<KIND, (MW < 0 ? 0 : MW)> B;
+  if constexpr (MW >= 0) {
+    if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fN) : a.W.bN, a.W.n, lane);
+  }
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
-    if (!last) {
+    if (!a.last) {
+      // The previous group's reads of gTl finished before this barrier pair
+      // lets the mixing overwrite it.
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? gvin[(e * NY + lm) * C + c] : 0.f;
+      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? a.gvin[(e * NY + lm) * C + c] : 0.f;
       __syncthreads();
-      mix_bwd<KIND, LMAX, WL>(gVl, gTl, epb, C, W);
+      if constexpr (MW >= 0)
+        mix32::mix_bwd<KIND, MW>(B, gVl, gTl, lane);
+      else
+        mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, a.W);
       __syncthreads();
     }
-    if (valid) {
-      const float* Y = geo + e * kGeo + kGeoY;
-      float V[NY], G[NY], gT[NT];
-      load_vprev<NY>(first, e, c, C, we1, ldwe, vprev, Y, V);
-      const int64_t i = ei[e];
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) G[lm] = gam[(i * NY + lm) * C + c];
-#pragma unroll
-      for (int k = 0; k < NT; ++k) gT[k] = last ? 0.f : gTl[(el * NT + k) * CP + c];
-      for_paths<LMAX>(last, [&](int, int, int l3, int toff, int qs, int) {
-        if (l3 == 0) gT[toff] += gs[e * ldgs + qs * C + c];
-      });
-      float gV[NY], gG[NY];
-#pragma unroll
-      for (int k = 0; k < NY; ++k) {
-        gV[k] = 0.f;
-        gG[k] = 0.f;
-      }
-      for_paths<LMAX>(last, [&](int l1, int l2, int l3, int toff, int, int) {
-#pragma unroll
-        for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
-          const float g = gT[toff + m3];
-#pragma unroll
-          for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
-#pragma unroll
-            for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
-              const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
-              if (cgv != 0.f) {
-                const float w = cgv * g;
-                gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
-                gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
-              }
-            }
-        }
-      });
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) ggc[(e * NY + lm) * C + c] = gG[lm];
-      if (!first) {
-#pragma unroll
-        for (int lm = 0; lm < NY; ++lm) gvout[(e * NY + lm) * C + c] = gV[lm];
-      } else {
-        // V0[c][lm] = w0[l][c] Y[lm]
-#pragma unroll
-        for (int l = 0; l <= LMAX; ++l) {
-          float gw = 0.f;
-          const float w0 = we1[e * ldwe + l * C + c];
-#pragma unroll
-          for (int m = 0; m < 2 * l + 1; ++m) {
-            gw += gV[l * l + m] * Y[l * l + m];
-            float part = w0 * gV[l * l + m];
-            for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-            if (c == 0) gY[e * 16 + l * l + m] += part;
-          }
-          gew[e * ldgew + l * C + c] = gw;
-        }
-      }
+    if (valid) tp_bwd_edge<LMAX>(a, e, c, gTl + el * NT * CP, CP);
+  }
+}
+
+// Adjoint of one layer's tensor product and, for t < T, of its channel mixing.
+template <int KIND, int LMAX, bool C32>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k_tp_bwd(TpBwdArgs a) {
+  if constexpr (C32) {
+    static_assert(LMAX == 2, "the 32-channel plan is for l <= 2");
+    switch (__builtin_amdgcn_readfirstlane(threadIdx.x >> 6)) {
+      case 0: tp_bwd_loop<KIND, LMAX, 0>(a); break;
+      case 1: tp_bwd_loop<KIND, LMAX, 1>(a); break;
+      case 2: tp_bwd_loop<KIND, LMAX, 2>(a); break;
+      default: tp_bwd_loop<KIND, LMAX, 3>(a); break;
     }
-    if (!last) __syncthreads();
+  } else {
+    tp_bwd_loop<KIND, LMAX, -1>(a);
   }
 }
 
@@ -881,22 +965,18 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
   const Dims& d = m->dims;
   Workspace& ws = ctx->ws;
   const bool last = t == d.T;
-  const MixPtrs W = layer_mix(m, t);
+  const TpFwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
+                    ws.s[t], d.nscal * d.C, layer_mix(m, t), ws.V[t]};
   const unsigned grid = tp_grid(ws, d.C);
+  const size_t lds = tp_lds_bytes(d.C, d.L, false);
   const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1]);
-  // Staging the mixing weights in LDS halves the workgroups per CU and was
-  // measured slower than reading them through L1/L2, so it stays off.
-  const size_t wl_bytes = (size_t)W.n * 4;  // FP32 copy or BF16 hi | lo halves
-  const bool wl = false;
-#define NQ_TPF(K, LM)                                                                                    \
-  if (wl)                                                                                                \
-    k_tp_fwd<K, LM, true><<<grid, 256, wl_bytes, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
-                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.s[t],  \
-                                                  d.nscal * d.C, W, ws.V[t]);                               \
-  else                                                                                                   \
-  k_tp_fwd<K, LM, false><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, \
-                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.s[t],  \
-                                                  d.nscal * d.C, W, ws.V[t])
+  // the last layer has no mixing: the lighter generic kernel keeps more waves
+  const bool c32 = d.L == 2 && d.C == mix32::C && !last;
+#define NQ_TPF(K, LM)                                                           \
+  if (LM == 2 && c32)                                                           \
+    k_tp_fwd<K, 2, true><<<grid, 256, lds, ctx->stream>>>(a);                   \
+  else                                                                          \
+    k_tp_fwd<K, LM, false><<<grid, 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
     case 0: NQ_TPF(G_F32, 1); break;
     case 1: NQ_TPF(G_F32, 2); break;
@@ -914,22 +994,19 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const Dims& d = m->dims;
   Workspace& ws = ctx->ws;
   const bool last = t == d.T;
-  const MixPtrs W = layer_mix(m, t);
+  const TpBwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
+                    ws.gs, d.nscal * d.C, last ? nullptr : gvin, layer_mix(m, t), ws.ggc, gvout, ws.gew,
+                    2 * d.NW, ws.gY};
   const unsigned grid = tp_grid(ws, d.C);
+  const size_t lds = tp_lds_bytes(d.C, d.L, true);
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1]);
-  const size_t wl_bytes = (size_t)W.n * 4;
-  const bool wl = false;
-#define NQ_TPB(K, LM)                                                                                     \
-  if (wl)                                                                                                 \
-    k_tp_bwd<K, LM, true><<<grid, 256, wl_bytes, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
-                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.gs,     \
-                                                  d.nscal * d.C, last ? nullptr : gvin, W, ws.ggc, gvout,    \
-                                                  ws.gew, 2 * d.NW, ws.gY);                                  \
-  else                                                                                                    \
-  k_tp_bwd<K, LM, false><<<grid, 256, 0, ctx->stream>>>(ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1,  \
-                                                  last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t], ws.gs,     \
-                                                  d.nscal * d.C, last ? nullptr : gvin, W, ws.ggc, gvout,    \
-                                                  ws.gew, 2 * d.NW, ws.gY)
+  // the last layer has no mixing: the lighter generic kernel keeps more waves
+  const bool c32 = d.L == 2 && d.C == mix32::C && !last;
+#define NQ_TPB(K, LM)                                                           \
+  if (LM == 2 && c32)                                                           \
+    k_tp_bwd<K, 2, true><<<grid, 256, lds, ctx->stream>>>(a);                   \
+  else                                                                          \
+    k_tp_bwd<K, LM, false><<<grid, 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
     case 0: NQ_TPB(G_F32, 1); break;
     case 1: NQ_TPB(G_F32, 2); break;
@@ -1182,7 +1259,6 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
   gemm(ctx, m, m->v0e1, false, a_plain(ws.x[0], d.D, d.D), e_store(ws.we1, 2 * d.NW, 2 * d.NW), "fwd.v0env1");
   const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
   for (int t = 1; t <= d.T; ++t) {
-    const bool last = t == d.T;
     if (t > 1)
       gemm(ctx, m, *m->env[t - 1], false, a_plain(ws.x[t - 1], d.D, d.D), e_store(ws.e[t], d.NW, d.NW),
            "fwd.env" + std::to_string(t));
@@ -1274,10 +1350,8 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
       gout = dst;
     }
   }
-  const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
   int gvcur = 0;  // ws.gv[gvcur] holds dE/dV_t while processing layer t (t < T)
   for (int t = d.T; t >= 1; --t) {
-    const bool last = t == d.T;
     const int kl = d.n_lat - 1;
     {
       const int sp_ = span_begin(ctx, "rowdot_gu" + std::to_string(t));
