@@ -31,39 +31,58 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 enum ALoadMode { A_PLAIN = 0, A_SILU = 1, A_CAT = 2, A_GRADSILU = 3 };
 
+// Raw loads of four consecutive A values of one row, kept in registers until
+// the tile is written to LDS (a K step later), so the loads stay in flight
+// while the matrix cores work.
+struct ARaw {
+  float4 v, a;  // source values; the stored pre-activation (A_GRADSILU)
+  float f;      // row scale (A_GRADSILU)
+};
+
 struct ALoad {
   int mode;
   const float* p0; int ld0; int K0;  // primary source
   const float* p1; int ld1; int K1;  // concatenated source, or the pre-activation for A_GRADSILU
   const float* rs; int rs_ld;        // optional per-row scale (the cutoff u)
   float c;                           // constant factor (A_GRADSILU)
-  // Four consecutive columns k..k+3 of row r (k % 4 == 0; widths and leading
-  // dimensions are multiples of 4, so every access is one aligned 16-byte load).
-  __device__ inline float4 load4(int64_t r, int k) const {
-    float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+  // Issues the loads of columns k..k+3 of row r (k % 4 == 0; widths and
+  // leading dimensions are multiples of 4, so each access is one aligned
+  // 16-byte load). r must be a valid row; a column beyond the source width
+  // reads column 0 and is zeroed by finish(). Only uniform branches, so the
+  // loads of several K steps can be in flight together.
+  __device__ inline void fetch(int64_t r, int k, ARaw& o) const {
     if (mode == A_CAT) {
-      if (k < K0)
-        v = *reinterpret_cast<const float4*>(p0 + r * ld0 + k);
-      else if (k < K0 + K1)
-        v = *reinterpret_cast<const float4*>(p1 + r * ld1 + (k - K0));
-    } else if (k < K0) {
-      v = *reinterpret_cast<const float4*>(p0 + r * ld0 + k);
-      if (mode == A_SILU) {
-        v.x = siluf(v.x);
-        v.y = siluf(v.y);
-        v.z = siluf(v.z);
-        v.w = siluf(v.w);
-      } else if (mode == A_GRADSILU) {
-        const float4 a = *reinterpret_cast<const float4*>(p1 + r * ld1 + k);
-        float f = c;
-        if (rs) f *= rs[r * rs_ld];
-        v.x *= f * dsiluf(a.x);
-        v.y *= f * dsiluf(a.y);
-        v.z *= f * dsiluf(a.z);
-        v.w *= f * dsiluf(a.w);
+      const bool second = k >= K0;
+      const int k1 = k - K0 < K1 ? k - K0 : 0;
+      const float* p = second ? p1 + r * ld1 + k1 : p0 + r * ld0 + k;
+      o.v = *reinterpret_cast<const float4*>(p);
+    } else {
+      const int kk = k < K0 ? k : 0;
+      o.v = *reinterpret_cast<const float4*>(p0 + r * ld0 + kk);
+      if (mode == A_GRADSILU) {
+        o.a = *reinterpret_cast<const float4*>(p1 + r * ld1 + kk);
+        o.f = rs ? rs[r * rs_ld] : 1.f;
       }
     }
-    return v;
+  }
+  // The A values from the raw loads: zero outside the rows or columns,
+  // SiLU, or the adjoint g * c * rowscale * SiLU'(a).
+  __device__ inline float4 finish(const ARaw& o, bool row_ok, int k) const {
+    float4 v = o.v;
+    if (mode == A_SILU) {
+      v.x = siluf(v.x);
+      v.y = siluf(v.y);
+      v.z = siluf(v.z);
+      v.w = siluf(v.w);
+    } else if (mode == A_GRADSILU) {
+      const float f = c * o.f;
+      v.x *= f * dsiluf(o.a.x);
+      v.y *= f * dsiluf(o.a.y);
+      v.z *= f * dsiluf(o.a.z);
+      v.w *= f * dsiluf(o.a.w);
+    }
+    const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
+    return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 };
 
@@ -76,45 +95,76 @@ struct Epi {
   const float* x; int ldx;
   const float* rs; int rs_ld;
   int D;
-  template <int MODE>
-  __device__ inline void apply(int64_t r, int c, float v) const {
-    if (c >= N0) return;
-    if constexpr (MODE == E_STORE) {
-      o0[r * ld0 + c] = v;
-    } else if constexpr (MODE == E_STORE_X0) {
-      o0[r * ld0 + c] = v;
-      o1[r * ld1 + c] = rs[r * rs_ld] * siluf(v);
-    } else if constexpr (MODE == E_RESIDUAL) {
-      o0[r * ld0 + c] = v;
-      o1[r * ld1 + c] = (x[r * ldx + c] + rs[r * rs_ld] * siluf(v)) * kInvSqrt2;
-    } else if constexpr (MODE == E_LATENT_BWD) {
-      if (c < D) {
-        float* q = o0 + r * ld0 + c;
-        *q = *q * kInvSqrt2 + v;
-      } else {
-        o1[r * ld1 + (c - D)] = v;
-      }
-    } else {
-      o0[r * ld0 + c] += v;
-    }
-  }
 };
 
 // Writes the accumulator tiles of one wavefront through epilogue mode MODE.
-// Lane l holds rows 4*(l/16)+q, column l%16 of every 16x16 tile.
+// Lane l holds rows 4*(l/16)+q, column l%16 of every 16x16 tile. The values
+// an epilogue reads (which may alias what it writes) are loaded for a block
+// of up to 4 tiles before any of its stores, with indices clamped into range,
+// so those loads are in flight together; only the stores are guarded.
 template <int MODE, int MI, int NI>
 __device__ inline void store_tiles(const Epi& ep, const floatx4 (&acc)[MI][NI], int64_t rbase, int cbase,
                                    int lane, int64_t nrows) {
+  constexpr bool kRS = MODE == E_STORE_X0 || MODE == E_RESIDUAL;
+  constexpr bool kIN = MODE == E_RESIDUAL || MODE == E_LATENT_BWD || MODE == E_ADD;
+  constexpr int JC = NI < 4 ? NI : 4;
 #pragma unroll
-  for (int i = 0; i < MI; ++i)
-#pragma unroll
-    for (int j = 0; j < NI; ++j)
+  for (int i = 0; i < MI; ++i) {
+    float rsv[4];
+    if constexpr (kRS) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int64_t row = rbase + i * 16 + (lane / 16) * 4 + q;
-        const int col = cbase + j * 16 + lane % 16;
-        if (row < nrows) ep.apply<MODE>(row, col, acc[i][j][q]);
+        const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
+        rsv[q] = ep.rs[(r < nrows ? r : nrows - 1) * ep.rs_ld];
       }
+    }
+#pragma unroll
+    for (int j0 = 0; j0 < NI; j0 += JC) {
+      float in[JC][4];
+      if constexpr (kIN) {
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+          for (int q = 0; q < 4; ++q) {
+            if (j0 + jj >= NI) continue;
+            const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
+            const int64_t rc = r < nrows ? r : nrows - 1;
+            const int c = cbase + (j0 + jj) * 16 + lane % 16;
+            const int cc = c < ep.N0 ? c : 0;
+            if constexpr (MODE == E_RESIDUAL) in[jj][q] = ep.x[rc * ep.ldx + cc];
+            else if constexpr (MODE == E_LATENT_BWD) in[jj][q] = ep.o0[rc * ep.ld0 + (cc < ep.D ? cc : 0)];
+            else in[jj][q] = ep.o0[rc * ep.ld0 + cc];
+          }
+      }
+#pragma unroll
+      for (int jj = 0; jj < JC; ++jj)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int j = j0 + jj;
+          if (j >= NI) continue;
+          const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
+          const int c = cbase + j * 16 + lane % 16;
+          if (r >= nrows || c >= ep.N0) continue;
+          const float v = acc[i][j][q];
+          if constexpr (MODE == E_STORE) {
+            ep.o0[r * ep.ld0 + c] = v;
+          } else if constexpr (MODE == E_STORE_X0) {
+            ep.o0[r * ep.ld0 + c] = v;
+            ep.o1[r * ep.ld1 + c] = rsv[q] * siluf(v);
+          } else if constexpr (MODE == E_RESIDUAL) {
+            ep.o0[r * ep.ld0 + c] = v;
+            ep.o1[r * ep.ld1 + c] = (in[jj][q] + rsv[q] * siluf(v)) * kInvSqrt2;
+          } else if constexpr (MODE == E_LATENT_BWD) {
+            if (c < ep.D)
+              ep.o0[r * ep.ld0 + c] = in[jj][q] * kInvSqrt2 + v;
+            else
+              ep.o1[r * ep.ld1 + (c - ep.D)] = v;
+          } else {
+            ep.o0[r * ep.ld0 + c] = in[jj][q] + v;
+          }
+        }
+    }
+  }
 }
 
 // Kinds of matrix-core product.
@@ -148,8 +198,10 @@ __device__ inline void split_bf16(const float* v, bf16x8& hi, bf16x8& lo) {
 
 // C[rows, NP] = A[rows, Kp] * Bt[NP, Kp]^T.  4 wavefronts as WM x WN.
 // For BF16X3, Bt holds two [NP][Kp] halves (hi, lo) and the product is
-// A_hi B_hi + A_lo B_hi + A_hi B_lo. The next K step's A and B tiles are
-// fetched into registers while the matrix cores work on the current one.
+// A_hi B_hi + A_lo B_hi + A_hi B_lo. The loads of the next K step's A and B
+// tiles are issued right after the barrier and consumed only after the
+// current step's matrix-core work (raw values in registers, transformed when
+// written to LDS), so HBM and L2 latency overlap the products.
 template <int KIND, int BM, int NP, int WM, int WN>
 __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<KIND>::BT* __restrict__ Bt,
                                               const int* __restrict__ nrows_p, ALoad ld, Epi ep) {
@@ -179,6 +231,7 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
   const int wave = tid / 64, lane = tid % 64;
   const int wm = wave / WN, wn = wave % WN;
   const int64_t half = (int64_t)NP * Kp;
+  const int nsteps = Kp / BK;
 
   floatx4 acc[MI][NI];
 #pragma unroll
@@ -186,19 +239,19 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
 #pragma unroll
     for (int j = 0; j < NI; ++j) acc[i][j] = floatx4{0.f, 0.f, 0.f, 0.f};
 
-  float4 ra[NA];
+  ARaw ra[NA];
   u32x4 rb[NB];
-#define NQ_GEMM_FETCH(K0)                                                                          \
+#define NQ_GEMM_FETCH_A(K0)                                                                        \
   {                                                                                               \
     _Pragma("unroll") for (int q = 0; q < NA; ++q) {                                              \
-      const int idx = tid + 256 * q;                                                              \
-      ra[q] = make_float4(0.f, 0.f, 0.f, 0.f);                                                    \
-      if (idx < A4) {                                                                             \
-        const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;                                 \
-        const int64_t row = r0 + rr;                                                              \
-        if (row < nrows) ra[q] = ld.load4(row, (K0) + kk);                                        \
-      }                                                                                           \
+      const int idx = (tid + 256 * q) % A4;                                                       \
+      const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;                                   \
+      const int64_t row = r0 + rr < nrows ? r0 + rr : nrows - 1;                                  \
+      ld.fetch(row, (K0) + kk, ra[q]);                                                            \
     }                                                                                             \
+  }
+#define NQ_GEMM_FETCH_B(K0)                                                                        \
+  {                                                                                               \
     _Pragma("unroll") for (int q = 0; q < NB; ++q) {                                              \
       const int idx = tid + 256 * q;                                                              \
       if (idx < B16) {                                                                            \
@@ -208,88 +261,95 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
       }                                                                                           \
     }                                                                                             \
   }
-  NQ_GEMM_FETCH(0);
-  for (int k0 = 0; k0 < Kp; k0 += BK) {
+  NQ_GEMM_FETCH_A(0);
+  NQ_GEMM_FETCH_B(0);
+  for (int st = 0; st < nsteps; ++st) {
 #pragma unroll
-    for (int q = 0; q < NA; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < A4) {
-        const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
-        if constexpr (sizeof(AT) == 4) {  // one 16-byte LDS store per float4
-          *reinterpret_cast<float4*>(&As[rr * LDA + kk]) = ra[q];
-        } else {                          // four BF16 in one 8-byte store
-          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-          bf16x4 v;
-          v[0] = (bf16)ra[q].x;
-          v[1] = (bf16)ra[q].y;
-          v[2] = (bf16)ra[q].z;
-          v[3] = (bf16)ra[q].w;
-          *reinterpret_cast<bf16x4*>(&As[rr * LDA + kk]) = v;
+      for (int q = 0; q < NA; ++q) {
+        const int idx = tid + 256 * q;
+        if (idx < A4) {
+          const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
+          const float4 v = ld.finish(ra[q], r0 + rr < nrows, st * BK + kk);
+          if constexpr (sizeof(AT) == 4) {  // one 16-byte LDS store per float4
+            *reinterpret_cast<float4*>(&As[rr * LDA + kk]) = v;
+          } else {                          // four BF16 in one 8-byte store
+            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+            bf16x4 b4;
+            b4[0] = (bf16)v.x;
+            b4[1] = (bf16)v.y;
+            b4[2] = (bf16)v.z;
+            b4[3] = (bf16)v.w;
+            *reinterpret_cast<bf16x4*>(&As[rr * LDA + kk]) = b4;
+          }
         }
       }
-    }
 #pragma unroll
-    for (int q = 0; q < NB; ++q) {
-      const int idx = tid + 256 * q;
-      if (idx < B16) {
-        const int h = idx / (NP * CPR), rem = idx % (NP * CPR);
-        const int n = rem / CPR, ch = rem % CPR;
-        *reinterpret_cast<u32x4*>(&Bs[(h * NP + n) * LDB + ch * EPC]) = rb[q];
-      }
-    }
-    __syncthreads();
-    if (k0 + BK < Kp) NQ_GEMM_FETCH(k0 + BK);
-    if constexpr (KIND == G_BF16) {
-      bf16x8 a[MI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i)
-        a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8]);
-#pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const bf16x8 b =
-            *reinterpret_cast<const bf16x8*>(&Bs[(wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8]);
-#pragma unroll
-        for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
-      }
-    } else if constexpr (KIND == G_BF16X3) {
-      bf16x8 ahi[MI], alo[MI];
-#pragma unroll
-      for (int i = 0; i < MI; ++i) {
-        const float* src = &As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8];
-        float v[8];
-        *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(src);
-        *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(src + 4);
-        split_bf16(v, ahi[i], alo[i]);
-      }
-#pragma unroll
-      for (int j = 0; j < NI; ++j) {
-        const int nb = (wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8;
-        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&Bs[nb]);
-        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&Bs[NP * LDB + nb]);
-#pragma unroll
-        for (int i = 0; i < MI; ++i) {
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo, acc[i][j], 0, 0, 0);
-          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi, acc[i][j], 0, 0, 0);
+      for (int q = 0; q < NB; ++q) {
+        const int idx = tid + 256 * q;
+        if (idx < B16) {
+          const int h = idx / (NP * CPR), rem = idx % (NP * CPR);
+          const int n = rem / CPR, ch = rem % CPR;
+          *reinterpret_cast<u32x4*>(&Bs[(h * NP + n) * LDB + ch * EPC]) = rb[q];
         }
       }
-    } else {
+      __syncthreads();
+      if (st + 1 < nsteps) {
+        NQ_GEMM_FETCH_A((st + 1) * BK);
+        NQ_GEMM_FETCH_B((st + 1) * BK);
+      }
+      if constexpr (KIND == G_BF16) {
+        bf16x8 a[MI];
 #pragma unroll
-      for (int kk = 0; kk < BK; kk += 4) {
-        float a[MI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i) a[i] = As[(wm * RW + i * 16 + lane % 16) * LDA + kk + lane / 16];
+        for (int i = 0; i < MI; ++i)
+          a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8]);
 #pragma unroll
         for (int j = 0; j < NI; ++j) {
-          const float b = Bs[(wn * CW + j * 16 + lane % 16) * LDB + kk + lane / 16];
+          const bf16x8 b =
+              *reinterpret_cast<const bf16x8*>(&Bs[(wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8]);
 #pragma unroll
-          for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+          for (int i = 0; i < MI; ++i)
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
+        }
+      } else if constexpr (KIND == G_BF16X3) {
+        bf16x8 ahi[MI], alo[MI];
+#pragma unroll
+        for (int i = 0; i < MI; ++i) {
+          const float* src = &As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8];
+          float v[8];
+          *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(src);
+          *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(src + 4);
+          split_bf16(v, ahi[i], alo[i]);
+        }
+#pragma unroll
+        for (int j = 0; j < NI; ++j) {
+          const int nb = (wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8;
+          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&Bs[nb]);
+          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&Bs[NP * LDB + nb]);
+#pragma unroll
+          for (int i = 0; i < MI; ++i) {
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo, acc[i][j], 0, 0, 0);
+            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi, acc[i][j], 0, 0, 0);
+          }
+        }
+      } else {
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+          float a[MI];
+#pragma unroll
+          for (int i = 0; i < MI; ++i) a[i] = As[(wm * RW + i * 16 + lane % 16) * LDA + kk + lane / 16];
+#pragma unroll
+          for (int j = 0; j < NI; ++j) {
+            const float b = Bs[(wn * CW + j * 16 + lane % 16) * LDB + kk + lane / 16];
+#pragma unroll
+            for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
+          }
         }
       }
-    }
-    __syncthreads();
+      __syncthreads();
   }
-#undef NQ_GEMM_FETCH
+#undef NQ_GEMM_FETCH_A
+#undef NQ_GEMM_FETCH_B
   const int64_t rbase = r0 + wm * RW;
   const int cbase = wn * CW;
   switch (ep.mode) {
