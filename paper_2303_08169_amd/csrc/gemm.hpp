@@ -45,6 +45,7 @@ struct ALoad {
   const float* p1; int ld1; int K1;  // concatenated source, or the pre-activation for A_GRADSILU
   const float* rs; int rs_ld;        // optional per-row scale (the cutoff u)
   float c;                           // constant factor (A_GRADSILU)
+  float* gu;                         // A_GRADSILU, optional: gu[r] += c * sum_k g[r][k] SiLU(a[r][k])
   // Issues the loads of columns k..k+3 of row r (k % 4 == 0; widths and
   // leading dimensions are multiples of 4, so each access is one aligned
   // 16-byte load). r must be a valid row; a column beyond the source width
@@ -67,7 +68,10 @@ struct ALoad {
   }
   // The A values from the raw loads: zero outside the rows or columns,
   // SiLU, or the adjoint g * c * rowscale * SiLU'(a).
-  __device__ inline float4 finish(const ARaw& o, bool row_ok, int k) const {
+  // With gu set, rd accumulates this chunk's share of sum_k g SiLU(a), the
+  // derivative with respect to the row scale, from the same loaded values.
+  __device__ inline float4 finish(const ARaw& o, bool row_ok, int k, float& rd) const {
+    const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
     float4 v = o.v;
     if (mode == A_SILU) {
       v.x = siluf(v.x);
@@ -76,12 +80,16 @@ struct ALoad {
       v.w = siluf(v.w);
     } else if (mode == A_GRADSILU) {
       const float f = c * o.f;
-      v.x *= f * dsiluf(o.a.x);
-      v.y *= f * dsiluf(o.a.y);
-      v.z *= f * dsiluf(o.a.z);
-      v.w *= f * dsiluf(o.a.w);
+      const float sx = sigmoidf_(o.a.x), sy = sigmoidf_(o.a.y), sz = sigmoidf_(o.a.z), sw = sigmoidf_(o.a.w);
+      if (gu) {
+        const float part = v.x * o.a.x * sx + v.y * o.a.y * sy + v.z * o.a.z * sz + v.w * o.a.w * sw;
+        rd += ok ? part : 0.f;
+      }
+      v.x *= f * sx * (1.f + o.a.x * (1.f - sx));
+      v.y *= f * sy * (1.f + o.a.y * (1.f - sy));
+      v.z *= f * sz * (1.f + o.a.z * (1.f - sz));
+      v.w *= f * sw * (1.f + o.a.w * (1.f - sw));
     }
-    const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
     return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
   }
 };
@@ -241,6 +249,9 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
 
   ARaw ra[NA];
   u32x4 rb[NB];
+  float rd[NA];  // row-scale derivative partial sums (ld.gu)
+#pragma unroll
+  for (int q = 0; q < NA; ++q) rd[q] = 0.f;
 #define NQ_GEMM_FETCH_A(K0)                                                                        \
   {                                                                                               \
     _Pragma("unroll") for (int q = 0; q < NA; ++q) {                                              \
@@ -269,7 +280,7 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
         const int idx = tid + 256 * q;
         if (idx < A4) {
           const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
-          const float4 v = ld.finish(ra[q], r0 + rr < nrows, st * BK + kk);
+          const float4 v = ld.finish(ra[q], r0 + rr < nrows, st * BK + kk, rd[q]);
           if constexpr (sizeof(AT) == 4) {  // one 16-byte LDS store per float4
             *reinterpret_cast<float4*>(&As[rr * LDA + kk]) = v;
           } else {                          // four BF16 in one 8-byte store
@@ -350,6 +361,20 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
   }
 #undef NQ_GEMM_FETCH_A
 #undef NQ_GEMM_FETCH_B
+  if (ld.gu) {
+    // the BK / 4 lanes that loaded one row are consecutive
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      float r = rd[q];
+#pragma unroll
+      for (int o = 1; o < BK / 4; o <<= 1) r += __shfl_xor(r, o);
+      const int idx = tid + 256 * q;
+      if (idx < A4 && idx % (BK / 4) == 0) {
+        const int64_t row = r0 + idx / (BK / 4);
+        if (row < nrows) ld.gu[row] += ld.c * r;
+      }
+    }
+  }
   const int64_t rbase = r0 + wm * RW;
   const int cbase = wn * CW;
   switch (ep.mode) {

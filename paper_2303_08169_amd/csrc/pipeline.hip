@@ -542,21 +542,6 @@ __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
   if (i < n) p[i] = v;
 }
 
-// gu[e] += c * sum_k g[e][k] * SiLU(a[e][k]); 16 lanes per edge.
-__global__ __launch_bounds__(256) void k_rowdot_gu(const int* __restrict__ nedge_p, const float* __restrict__ g,
-                                                   int ldg, const float* __restrict__ a, int lda, int K, float c,
-                                                   float* __restrict__ gu) {
-  const int64_t e = (int64_t)blockIdx.x * 16 + threadIdx.x / 16;
-  const int l = threadIdx.x % 16;
-  const bool valid = e < *nedge_p;
-  float acc = 0.f;
-  if (valid)
-    for (int k = l; k < K; k += 16) acc += g[e * ldg + k] * siluf(a[e * lda + k]);
-#pragma unroll
-  for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
-  if (valid && l == 0) gu[e] += c * acc;
-}
-
 struct TpBwdArgs {
   const int* nedge_p;
   const int* ei;
@@ -929,13 +914,14 @@ int gemm_variant_count(int prec, int NP) {
 
 namespace {
 
-ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
-ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f}; }
+ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }
+ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }
 ALoad a_cat(const float* p, int ld, int K, const float* q, int ldq, int Kq) {
-  return ALoad{A_CAT, p, ld, K, q, ldq, Kq, nullptr, 0, 1.f};
+  return ALoad{A_CAT, p, ld, K, q, ldq, Kq, nullptr, 0, 1.f, nullptr};
 }
-ALoad a_gradsilu(const float* g, int ldg, int K, const float* a, int lda, const float* rs, float c) {
-  return ALoad{A_GRADSILU, g, ldg, K, a, lda, 0, rs, kGeo, c};
+ALoad a_gradsilu(const float* g, int ldg, int K, const float* a, int lda, const float* rs, float c,
+                 float* gu = nullptr) {
+  return ALoad{A_GRADSILU, g, ldg, K, a, lda, 0, rs, kGeo, c, gu};
 }
 Epi e_store(float* o, int ld, int N) { return Epi{E_STORE, o, ld, N, nullptr, 0, nullptr, 0, nullptr, 0, 0}; }
 Epi e_add(float* o, int ld, int N) { return Epi{E_ADD, o, ld, N, nullptr, 0, nullptr, 0, nullptr, 0, 0}; }
@@ -1353,15 +1339,10 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
   int gvcur = 0;  // ws.gv[gvcur] holds dE/dV_t while processing layer t (t < T)
   for (int t = d.T; t >= 1; --t) {
     const int kl = d.n_lat - 1;
-    {
-      const int sp_ = span_begin(ctx, "rowdot_gu" + std::to_string(t));
-      k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_lat[t][kl], d.lat[kl], d.D, kInvSqrt2,
-                                                          ws.gu);
-      span_end(ctx, sp_);
-    }
     float* gout = nullptr;
     for (int k = kl; k >= 0; --k) {
-      ALoad ld = k == kl ? a_gradsilu(ws.gx, d.D, d.lat[k], ws.a_lat[t][k], d.lat[k], u, kInvSqrt2)
+      // the first product also adds dE/du of the residual update to gu
+      ALoad ld = k == kl ? a_gradsilu(ws.gx, d.D, d.lat[k], ws.a_lat[t][k], d.lat[k], u, kInvSqrt2, ws.gu)
                          : a_gradsilu(gout, ws.maxw, d.lat[k], ws.a_lat[t][k], d.lat[k], nullptr, 1.f);
       Epi ep;
       if (k == 0) {
@@ -1385,14 +1366,10 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
   }
   // two-body MLP: x0 = u SiLU(a_last)
   const int kt = d.n_tb - 1;
-  {
-    const int sp_ = span_begin(ctx, "rowdot_gu");
-    k_rowdot_gu<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.gx, d.D, ws.a_tb[kt], d.tb[kt], d.D, 1.f, ws.gu);
-    span_end(ctx, sp_);
-  }
   float* gout = nullptr;
   for (int k = kt; k >= 0; --k) {
-    ALoad ld = k == kt ? a_gradsilu(ws.gx, d.D, d.tb[k], ws.a_tb[k], d.tb[k], u, 1.f)
+    // the first product also adds dE/du of x0 = u SiLU(a) to gu
+    ALoad ld = k == kt ? a_gradsilu(ws.gx, d.D, d.tb[k], ws.a_tb[k], d.tb[k], u, 1.f, ws.gu)
                        : a_gradsilu(gout, ws.maxw, d.tb[k], ws.a_tb[k], d.tb[k], nullptr, 1.f);
     const int fin = k == 0 ? d.n_in2b : d.tb[k - 1];
     gemm(ctx, m, *m->tb[k], true, ld, e_store(ws.gh[k % 2], ws.maxw, fin), "bwd.twobody." + std::to_string(k));
