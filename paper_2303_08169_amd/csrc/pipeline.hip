@@ -136,6 +136,63 @@ __global__ __launch_bounds__(256) void k_env_fwd(int64_t n, const int* __restric
   }
 }
 
+// ------------------------------------------------------------------ group sums
+constexpr int spread_len(int n, int rounds) {
+  for (int r = 0; r < rounds; ++r) n = (n + 1) / 2;
+  return n;
+}
+
+// Sums N values per lane over each aligned group of W lanes (W a power of two
+// dividing 64) by recursive halving: every round trades the half of the
+// remaining components this lane does not keep for the partner's copy of the
+// half it keeps, so the N sums take about N + log2(W) shuffles instead of
+// N log2(W). Afterwards slot s < count of this lane holds the group total of
+// component first + s, and every component is held by exactly one lane.
+template <int N, int W>
+__device__ inline void spread_sum(float (&v)[N], int lane, int& first, int& count) {
+  first = 0;
+  int len = N;
+#pragma unroll
+  for (int r = 0; (W >> (r + 1)) >= 1; ++r) {
+    const int m = W >> (r + 1);
+    const int L = spread_len(N, r), H = (L + 1) / 2;
+    const bool up = (lane & m) != 0;
+    float nv[N];
+#pragma unroll
+    for (int i = 0; i < N; ++i) nv[i] = 0.f;
+#pragma unroll
+    for (int i = 0; i < H; ++i) {
+      const float hi = H + i < L ? v[H + i] : 0.f;
+      const float send = up ? v[i] : hi;
+      nv[i] = (up ? hi : v[i]) + __shfl_xor(send, m, W);
+    }
+#pragma unroll
+    for (int i = 0; i < N; ++i) v[i] = nv[i];
+    if (up) {
+      first += H;
+      len -= H;
+    } else {
+      len = len < H ? len : H;
+    }
+  }
+  count = len > 0 ? len : 0;
+}
+
+// dst[k] += sum over the C lanes of the group (lane index c) of v[k], k < N.
+template <int N>
+__device__ inline void add_group_sums(float (&v)[N], int C, int c, float* dst) {
+  int first = 0, count = 0;
+  switch (C) {
+    case 8: spread_sum<N, 8>(v, c, first, count); break;
+    case 16: spread_sum<N, 16>(v, c, first, count); break;
+    case 32: spread_sum<N, 32>(v, c, first, count); break;
+    default: spread_sum<N, 64>(v, c, first, count); break;
+  }
+#pragma unroll
+  for (int k = 0; k < N; ++k)
+    if (k < count) dst[first + k] += v[k];
+}
+
 // ------------------------------------------------------------------ tensor products
 // Compile-time walk over the coupling paths (l1,l2,l3) of one layer in
 // lexicographic order. `f(l1,l2,l3,toff,qscal,pidx_in_l3)` is called for each
@@ -607,7 +664,9 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) a.gvout[(e * NY + lm) * C + c] = gV[lm];
   } else {
-    // V0[c][lm] = w0[l][c] Y[lm]
+    // V0[c][lm] = w0[l][c] Y[lm]. The channel sums for dE/dY reduce each
+    // component right away: gathering all of them first for add_group_sums
+    // raises the register peak of the 32-channel kernel into spills.
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       float gw = 0.f;
@@ -721,7 +780,7 @@ __global__ __launch_bounds__(256) void k_env_bwd_edge(const int* __restrict__ ne
   if (e >= *nedge_p) return;
   const int64_t i = ei[e];
   const float* Y = geo + e * kGeo + kGeoY;
-  float ev[L + 1];
+  float ev[L + 1], prod[NY];
 #pragma unroll
   for (int l = 0; l <= L; ++l) ev[l] = esrc[e * lde + l * C + c];
 #pragma unroll
@@ -731,12 +790,11 @@ __global__ __launch_bounds__(256) void k_env_bwd_edge(const int* __restrict__ ne
     for (int m = 0; m < 2 * l + 1; ++m) {
       const float gg = ggam[(i * NY + l * l + m) * C + c];
       ge += gg * Y[l * l + m];
-      float prod = ev[l] * gg;
-      for (int o = C / 2; o >= 1; o >>= 1) prod += __shfl_xor(prod, o, C);
-      if (c == 0) gY[e * 16 + l * l + m] += prod;
+      prod[l * l + m] = ev[l] * gg;
     }
     gew[e * ldgew + gcol + l * C + c] = ge;
   }
+  add_group_sums<NY>(prod, C, c, gY + e * 16);
 }
 
 __device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, float& gx, float& gy, float& gz) {
