@@ -189,6 +189,7 @@ nq_status nq_ctx_create(int device, void* hip_stream, nq_ctx** out) {
     nq_ctx* c = new nq_ctx();
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
+    NQ_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
     *out = c;
   });
 }

@@ -179,6 +179,7 @@ struct Span {
 
 struct nq_ctx {
   int device = 0;
+  int num_cu = 256;  // compute units of the device
   hipStream_t stream = nullptr;
   std::string last_error;
   nq::NbrList nl;

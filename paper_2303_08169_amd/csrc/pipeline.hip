@@ -18,6 +18,9 @@
 // sum over its edges of g(a,j) - g(j,a) through the reverse-edge index, so no
 // atomics are needed and the result is deterministic.
 #include <cmath>
+#include <map>
+#include <mutex>
+#include <utility>
 
 #include "cg_const.hpp"
 #include "gemm.hpp"
@@ -619,21 +622,36 @@ struct TpBwdArgs {
   float* gY;
 };
 
-// Adjoint of the tensor product of one (edge, channel), given dE/dT from the
-// mixing adjoint (gTrow: this edge's rows in LDS, null for the last layer) and
-// dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i, and
-// either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and the
-// w0 part of dE/dY into gY.
+// Inputs of the adjoint of one (edge, channel) that do not depend on the
+// mixing adjoint: V_{t-1}, Gamma_i and dE/ds. They are loaded before the
+// group's mixing so that their HBM latency overlaps it.
+template <int LMAX> struct TpBwdIn {
+  static constexpr int NY = TPSize<LMAX>::NY, NS = LMAX + 1;  // scalar paths: (l, l, 0)
+  float V[NY], G[NY], gs[NS];
+};
+
 template <int LMAX>
-__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP) {
+__device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int c, TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = a.C;
-  const float* Y = a.geo + e * kGeo + kGeoY;
-  float V[NY], G[NY];
-  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, Y, V);
+  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
   const int64_t i = a.ei[e];
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) G[lm] = a.gam[(i * NY + lm) * C + c];
+  for (int lm = 0; lm < NY; ++lm) in.G[lm] = a.gam[(i * NY + lm) * C + c];
+#pragma unroll
+  for (int q = 0; q <= LMAX; ++q) in.gs[q] = a.gs[e * a.ldgs + q * C + c];
+}
+
+// Adjoint of the tensor product of one (edge, channel), given dE/dT from the
+// mixing adjoint (gTrow: this edge's rows in LDS, unused for the last layer)
+// and dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i,
+// and either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
+// the w0 part of dE/dY into gY.
+template <int LMAX>
+__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP,
+                                   const TpBwdIn<LMAX>& in) {
+  constexpr int NY = TPSize<LMAX>::NY;
+  const int C = a.C;
   float gV[NY], gG[NY];
 #pragma unroll
   for (int k = 0; k < NY; ++k) {
@@ -644,7 +662,7 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
 #pragma unroll
     for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
       float g = a.last ? 0.f : gTrow[(toff + m3) * CP + c];
-      if (l3 == 0) g += a.gs[e * a.ldgs + qs * C + c];
+      if (l3 == 0) g += in.gs[qs];
 #pragma unroll
       for (int m1 = 0; m1 < 2 * l1 + 1; ++m1)
 #pragma unroll
@@ -652,8 +670,8 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
           const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
           if (cgv != 0.f) {
             const float w = cgv * g;
-            gV[l1 * l1 + m1] += w * G[l2 * l2 + m2];
-            gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
+            gV[l1 * l1 + m1] += w * in.G[l2 * l2 + m2];
+            gG[l2 * l2 + m2] += w * in.V[l1 * l1 + m1];
           }
         }
     }
@@ -667,6 +685,7 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
     // V0[c][lm] = w0[l][c] Y[lm]. The channel sums for dE/dY reduce each
     // component right away: gathering all of them first for add_group_sums
     // raises the register peak of the 32-channel kernel into spills.
+    const float* Y = a.geo + e * kGeo + kGeoY;
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       float gw = 0.f;
@@ -703,11 +722,19 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
+    const int64_t ec = valid ? e : ne - 1;  // loads of a row past the end read the last edge
+    float gv[NY];
+    if (!a.last) {
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) gv[lm] = a.gvin[(ec * NY + lm) * C + c];
+    }
+    TpBwdIn<LMAX> in;
+    tp_bwd_load<LMAX>(a, ec, c, in);
     if (!a.last) {
       // The previous group's reads of gTl finished before this barrier pair
       // lets the mixing overwrite it.
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? a.gvin[(e * NY + lm) * C + c] : 0.f;
+      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? gv[lm] : 0.f;
       __syncthreads();
       if constexpr (MW >= 0)
         mix32::mix_bwd<KIND, MW>(B, gVl, gTl, lane);
@@ -715,7 +742,7 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
         mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, a.W);
       __syncthreads();
     }
-    if (valid) tp_bwd_edge<LMAX>(a, e, c, gTl + el * NT * CP, CP);
+    if (valid) tp_bwd_edge<LMAX>(a, e, c, gTl + el * NT * CP, CP, in);
   }
 }
 
@@ -999,10 +1026,22 @@ MixPtrs layer_mix(const nq_model* m, int t) {
   return w;
 }
 
-// Persistent launches: enough workgroups to fill the chip, each looping over
-// groups of edges.
-unsigned tp_grid(const Workspace& ws, int C) {
-  return (unsigned)std::min<int64_t>(grid_for(ws.cap, 256 / C), 4096);
+// Persistent launches: exactly as many workgroups as the chip holds at once
+// (no partial last wave of workgroups), each looping over groups of edges.
+template <class K>
+unsigned tp_grid(const nq_ctx* ctx, K kernel, size_t lds, int C) {
+  static std::map<std::pair<const void*, size_t>, int> cache;  // workgroups per CU
+  static std::mutex mu;                                         // contexts may live on several threads
+  std::lock_guard<std::mutex> lock(mu);
+  const auto key = std::make_pair(reinterpret_cast<const void*>(kernel), lds);
+  auto it = cache.find(key);
+  if (it == cache.end()) {
+    int per_cu = 0;
+    NQ_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, 256, lds));
+    it = cache.emplace(key, std::max(per_cu, 1)).first;
+  }
+  const int64_t resident = (int64_t)it->second * ctx->num_cu;
+  return (unsigned)std::max<int64_t>(1, std::min<int64_t>(grid_for(ctx->ws.cap, 256 / C), resident));
 }
 
 void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
@@ -1011,16 +1050,15 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
   const bool last = t == d.T;
   const TpFwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
                     ws.s[t], d.nscal * d.C, layer_mix(m, t), ws.V[t]};
-  const unsigned grid = tp_grid(ws, d.C);
   const size_t lds = tp_lds_bytes(d.C, d.L, false);
   const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1]);
   // the last layer has no mixing: the lighter generic kernel keeps more waves
   const bool c32 = d.L == 2 && d.C == mix32::C && !last;
-#define NQ_TPF(K, LM)                                                           \
-  if (LM == 2 && c32)                                                           \
-    k_tp_fwd<K, 2, true><<<grid, 256, lds, ctx->stream>>>(a);                   \
-  else                                                                          \
-    k_tp_fwd<K, LM, false><<<grid, 256, lds, ctx->stream>>>(a)
+#define NQ_TPF(K, LM)                                                                             \
+  if (LM == 2 && c32)                                                                             \
+    k_tp_fwd<K, 2, true><<<tp_grid(ctx, k_tp_fwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else                                                                                            \
+    k_tp_fwd<K, LM, false><<<tp_grid(ctx, k_tp_fwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
     case 0: NQ_TPF(G_F32, 1); break;
     case 1: NQ_TPF(G_F32, 2); break;
@@ -1041,16 +1079,15 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const TpBwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
                     ws.gs, d.nscal * d.C, last ? nullptr : gvin, layer_mix(m, t), ws.ggc, gvout, ws.gew,
                     2 * d.NW, ws.gY};
-  const unsigned grid = tp_grid(ws, d.C);
   const size_t lds = tp_lds_bytes(d.C, d.L, true);
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1]);
   // the last layer has no mixing: the lighter generic kernel keeps more waves
   const bool c32 = d.L == 2 && d.C == mix32::C && !last;
-#define NQ_TPB(K, LM)                                                           \
-  if (LM == 2 && c32)                                                           \
-    k_tp_bwd<K, 2, true><<<grid, 256, lds, ctx->stream>>>(a);                   \
-  else                                                                          \
-    k_tp_bwd<K, LM, false><<<grid, 256, lds, ctx->stream>>>(a)
+#define NQ_TPB(K, LM)                                                                             \
+  if (LM == 2 && c32)                                                                             \
+    k_tp_bwd<K, 2, true><<<tp_grid(ctx, k_tp_bwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else                                                                                            \
+    k_tp_bwd<K, LM, false><<<tp_grid(ctx, k_tp_bwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
     case 0: NQ_TPB(G_F32, 1); break;
     case 1: NQ_TPB(G_F32, 2); break;
