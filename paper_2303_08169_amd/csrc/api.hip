@@ -25,7 +25,8 @@ static hipEvent_t pool_event(nq_ctx* ctx) {
   return e;
 }
 
-int span_begin(nq_ctx* ctx, const std::string& name, double fpe, double bpe, double fpa, double bpa) {
+int span_begin(nq_ctx* ctx, const std::string& name, double fpe, double bpe, double fpa, double bpa,
+               double mfpe) {
   if (!ctx->timing) return -1;
   Span s;
   s.name = name;
@@ -35,6 +36,7 @@ int span_begin(nq_ctx* ctx, const std::string& name, double fpe, double bpe, dou
   s.byte_per_edge = bpe;
   s.flop_per_atom = fpa;
   s.byte_per_atom = bpa;
+  s.mfma_flop_per_edge = mfpe;
   NQ_HIP(hipEventRecord(s.a, ctx->stream));
   ctx->spans.push_back(s);
   return (int)ctx->spans.size() - 1;
@@ -522,7 +524,7 @@ nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
     if (ctx->ws.nedge.p) NQ_HIP(hipMemcpy(&ne, ctx->ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost));
     struct Agg {
       int count = 0;
-      double ms = 0, flop = 0, byte = 0;
+      double ms = 0, flop = 0, byte = 0, mfma = 0;
     };
     std::vector<std::string> order;
     std::vector<Agg> agg;
@@ -539,6 +541,7 @@ nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
       agg[k].ms += ms;
       agg[k].flop = s.flop_per_edge * ne + s.flop_per_atom * (double)ctx->ws.n_atoms;
       agg[k].byte = s.byte_per_edge * ne + s.byte_per_atom * (double)ctx->ws.n_atoms;
+      agg[k].mfma = s.mfma_flop_per_edge * ne;
       ctx->event_pool.push_back(s.a);
       ctx->event_pool.push_back(s.b);
     }
@@ -548,8 +551,8 @@ nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
     for (size_t k = 0; k < order.size(); ++k) {
       std::snprintf(tmp, sizeof(tmp),
                     "%s{\"name\": \"%s\", \"count\": %d, \"ms_total\": %.6f, \"flop_per_launch\": %.6e, "
-                    "\"bytes_per_launch\": %.6e}",
-                    k ? ", " : "", order[k].c_str(), agg[k].count, agg[k].ms, agg[k].flop, agg[k].byte);
+                    "\"mfma_flop_per_launch\": %.6e, \"bytes_per_launch\": %.6e}",
+                    k ? ", " : "", order[k].c_str(), agg[k].count, agg[k].ms, agg[k].flop, agg[k].mfma, agg[k].byte);
       out += tmp;
     }
     out += "]}";

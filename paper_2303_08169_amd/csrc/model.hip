@@ -391,6 +391,7 @@ nq_model* model_create(nq_ctx* ctx, const nq_model_desc* desc, const double* w, 
       }
       m->tp_flop_fwd.push_back(cgf + mixf);
       m->tp_flop_bwd.push_back(2.0 * cgf + mixf);
+      m->tp_flop_mix.push_back(mixf);
     }
     // the kernels carry the compile-time table; it must agree with this derivation
     for (int a = 0; a <= kMaxL; ++a)

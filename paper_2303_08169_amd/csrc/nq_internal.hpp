@@ -115,6 +115,7 @@ struct nq_model {
   nq::DevBuf wout;                          // [edge_last] f32 final edge weights
   std::vector<nq::MixW*> mixw;              // per layer t < T (index t-1)
   std::vector<double> tp_flop_fwd, tp_flop_bwd;  // algorithmic FLOPs per edge of each layer's tensor product
+  std::vector<double> tp_flop_mix;               // ... of which the channel mixing (matrix cores), each direction
   mutable std::map<std::string, int> gemm_choice;  // tuned tile shape per matrix-core product
   ~nq_model();
 };
@@ -174,6 +175,7 @@ struct Span {
   hipEvent_t a = nullptr, b = nullptr;
   double flop_per_edge = 0, byte_per_edge = 0;  // algorithmic work per in-cutoff edge
   double flop_per_atom = 0, byte_per_atom = 0;  // ... or per atom
+  double mfma_flop_per_edge = 0;                // part of flop_per_edge done on the matrix cores
 };
 }  // namespace nq
 
@@ -233,7 +235,7 @@ void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int
 
 // Start/stop a timed span on ctx->stream (no-ops unless timing is enabled).
 int span_begin(nq_ctx* ctx, const std::string& name, double flop_per_edge = 0, double byte_per_edge = 0,
-               double flop_per_atom = 0, double byte_per_atom = 0);
+               double flop_per_atom = 0, double byte_per_atom = 0, double mfma_flop_per_edge = 0);
 void span_end(nq_ctx* ctx, int idx);
 
 inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }

@@ -960,12 +960,33 @@ void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, 
 #undef NQ_G
 }
 
+// Algorithmic HBM bytes per edge row of one product: every source value of A
+// read once, every value the epilogue reads or writes once.
+double gemm_bytes_per_row(const ALoad& ld, const Epi& ep) {
+  double a = 0;
+  switch (ld.mode) {
+    case A_CAT: a = ld.K0 + ld.K1; break;
+    case A_GRADSILU: a = (ld.ld0 ? ld.K0 : 0) + ld.K0 + (ld.rs ? 1 : 0) + (ld.gu ? 2 : 0); break;
+    default: a = ld.K0;
+  }
+  double o = 0;
+  switch (ep.mode) {
+    case E_STORE: o = ep.N0; break;
+    case E_STORE_X0: o = 2.0 * ep.N0 + 1; break;
+    case E_RESIDUAL: o = 3.0 * ep.N0 + 1; break;
+    case E_LATENT_BWD: o = ep.D + ep.N0; break;
+    default: o = 2.0 * ep.N0;
+  }
+  return 4.0 * (a + o);
+}
+
 // y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map. The tile shape
 // is the model's tuned choice for this product (or the one being timed).
 void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep,
           const std::string& name) {
   const Workspace& ws = ctx->ws;
-  const int sp = span_begin(ctx, name, 2.0 * L.fin * L.fout, 4.0 * (L.fin + L.fout));
+  const double flop = 2.0 * L.fin * L.fout;
+  const int sp = span_begin(ctx, name, flop, gemm_bytes_per_row(ld, ep), 0, 0, flop);
   const int NP = bwd ? L.np_b : L.np_f;
   const int Kp = bwd ? L.kp_b : L.kp_f;
   const int* nr = ws.v_nedge;
@@ -1051,7 +1072,12 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
   const TpFwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
                     ws.s[t], d.nscal * d.C, layer_mix(m, t), ws.V[t]};
   const size_t lds = tp_lds_bytes(d.C, d.L, false);
-  const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1]);
+  // bytes per edge: V_{t-1} (w0 and Y for t = 1), the centre index, s, V_t;
+  // per atom: Gamma read once
+  const double vin = t == 1 ? 4.0 * (d.NW + d.NY) : 4.0 * d.NY * d.C;
+  const double bpe = vin + 4.0 + 4.0 * d.nscal * d.C + (last ? 0.0 : 4.0 * d.NY * d.C);
+  const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1], bpe, 0,
+                            4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
   // the last layer has no mixing: the lighter generic kernel keeps more waves
   const bool c32 = d.L == 2 && d.C == mix32::C && !last;
 #define NQ_TPF(K, LM)                                                                             \
@@ -1080,7 +1106,14 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
                     ws.gs, d.nscal * d.C, last ? nullptr : gvin, layer_mix(m, t), ws.ggc, gvout, ws.gew,
                     2 * d.NW, ws.gY};
   const size_t lds = tp_lds_bytes(d.C, d.L, true);
-  const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1]);
+  // bytes per edge: dE/dV_t, V_{t-1} (w0 and Y for t = 1), the centre index,
+  // dE/ds, the dE/dGamma contributions, and dE/dV_{t-1} (t > 1) or dE/dw0
+  // plus the read-modify-write of dE/dY (t = 1); per atom: Gamma read once
+  const double vin = t == 1 ? 4.0 * (d.NW + d.NY) : 4.0 * d.NY * d.C;
+  const double vout = t == 1 ? 4.0 * d.NW + 8.0 * d.NY : 4.0 * d.NY * d.C;
+  const double bpe = (last ? 0.0 : 4.0 * d.NY * d.C) + vin + 4.0 + 4.0 * d.nscal * d.C + 4.0 * d.NY * d.C + vout;
+  const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1], bpe, 0,
+                            4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
   // the last layer has no mixing: the lighter generic kernel keeps more waves
   const bool c32 = d.L == 2 && d.C == mix32::C && !last;
 #define NQ_TPB(K, LM)                                                                             \
@@ -1108,7 +1141,8 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
   const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
   const int lde = t == 1 ? 2 * d.NW : d.NW;
   const float scale = (float)d.inv_sqrt_nu;
-  int sp = span_begin(ctx, "env_reduce" + std::to_string(t));
+  // per edge: the dE/dGamma contributions; per atom: dE/dGamma written, offsets
+  int sp = span_begin(ctx, "env_reduce" + std::to_string(t), 0, 4.0 * d.NY * d.C, 0, 4.0 * d.NY * d.C + 4.0);
   if (d.L == 1)
     k_env_reduce<4><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
                                                               scale, ws.ggam);
@@ -1116,7 +1150,9 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
     k_env_reduce<9><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
                                                               scale, ws.ggam);
   span_end(ctx, sp);
-  sp = span_begin(ctx, "env_bwd" + std::to_string(t));
+  // per edge: centre index, e, Y, dE/de written, dE/dY read-modify-write; per atom: dE/dGamma
+  sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0, 4.0 + 8.0 * d.NW + 4.0 * d.NY + 8.0 * d.NY, 0,
+                  4.0 * d.NY * d.C);
   if (d.L == 1)
     k_env_bwd_edge<4><<<grid_for(ws.cap, 256 / d.C), 256, 0, ctx->stream>>>(
         ws.v_nedge, ws.v_ei, ws.ggam, esrc, lde, ws.geo, d.C, ws.gew, 2 * d.NW, d.NW, ws.gY);
@@ -1317,7 +1353,8 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
   const int64_t cap = ws.cap;
   const float* u = ws.geo + 1;
   {
-    const int sp_ = span_begin(ctx, "geometry");
+    // per edge: r_ij and d, indices, species, geo row and two-body input row written
+    const int sp_ = span_begin(ctx, "geometry", 0, 16.0 + 8.0 + 8.0 + 4.0 * kGeo + 4.0 * ws.K0p);
     k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.v_rij, ws.v_ei, ws.v_ej, ws.v_a0,
                                                         species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
                                                    ctx->nl.flags.as<int>());
@@ -1347,14 +1384,16 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
     const int lde = t == 1 ? 2 * d.NW : d.NW;
     if (d.L == 1)
       {
-        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
+        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t), 0, 4.0 * d.NW + 4.0 * d.NY, 0,
+                                   4.0 * d.NY * d.C + 4.0);
         k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
                                                           ws.gam[t]);
         span_end(ctx, sp_);
       }
     else
       {
-        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t));
+        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t), 0, 4.0 * d.NW + 4.0 * d.NY, 0,
+                                   4.0 * d.NY * d.C + 4.0);
         k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
                                                           ws.gam[t]);
         span_end(ctx, sp_);
@@ -1385,7 +1424,7 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
   }
   const int ke = d.n_edge - 1;
   {
-    const int sp_ = span_begin(ctx, "edge_energy");
+    const int sp_ = span_begin(ctx, "edge_energy", 0, 4.0 * d.edge[ke] + 4.0);
     k_edge_energy<<<grid_for(cap, 16), 256, 0, s>>>(ne, ws.a_edge[ke], d.edge[ke], d.edge[ke],
                                                           m->wout.as<float>(), (float)d.sigma_e, ws.eij);
     span_end(ctx, sp_);
@@ -1471,7 +1510,8 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     gout = ws.gh[k % 2];
   }
   {
-    const int sp_ = span_begin(ctx, "geometry_bwd");
+    // per edge: geo row, gu, dE/dY, dE/db, the edge slot, g_ij written
+    const int sp_ = span_begin(ctx, "geometry_bwd", 0, 4.0 * kGeo + 4.0 + 4.0 * d.NY + 4.0 * d.nb + 4.0 + 16.0);
     k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
                                                             d.p, (float)d.rc, d.NY, ws.v_e0, ws.gr);
     span_end(ctx, sp_);
