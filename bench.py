@@ -182,14 +182,18 @@ def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
     from synth import weight_blob
     from synth.nh3 import masses, maxwell_boltzmann
 
-    segs, _ = B.weight_layout(B.make_desc(cf.model, args.precision))
+    import dataclasses
+
+    model = dataclasses.replace(cf.model, energy_scale=cf.model.energy_scale * args.md_energy_scale)
+    segs, _ = B.weight_layout(B.make_desc(model, args.precision))
     w = weight_blob(cf.weight_seed, segs)
-    pot = Potential(cf.model, w, args.precision)
+    pot = Potential(model, w, args.precision)
     dev = torch.device("cuda", 0)
     P = torch.tensor(pos, device=dev)
-    V = torch.tensor(maxwell_boltzmann(z, 300.0, 200), device=dev)
+    V = torch.tensor(maxwell_boltzmann(z, args.md_temp, 200), device=dev)
     IM = torch.tensor(1.0 / masses(z), device=dev)
     Z = torch.tensor(z, dtype=torch.int32, device=dev)
+    pot.neighbor_build(P, box, skin=args.md_skin)
     E, F = pot.energy_forces(P, Z, box)
     ep = torch.zeros(chunk, dtype=torch.float64, device=dev)
     ek = torch.zeros(chunk, dtype=torch.float64, device=dev)
@@ -212,7 +216,9 @@ def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
     _, rebuilds = pot.stats() if err is None else (0, -1)
     etot = np.array(epot) + np.array(ekin)
     out = {"md_steps_requested": args.md, "md_steps_done": done, "dt_fs": dt_fs, "precision": args.precision,
-           "workload": args.workload, "atoms": cf.n_atoms, "error": err, "rebuilds": rebuilds}
+           "workload": args.workload, "atoms": cf.n_atoms, "T0_K": args.md_temp,
+           "energy_scale_factor": args.md_energy_scale, "skin_A": args.md_skin, "error": err,
+           "rebuilds": rebuilds}
     if done:
         t = np.arange(1, done + 1) * dt_fs * 1e-3  # ps
         slope = np.polyfit(t, (etot - etot[0]) / cf.n_atoms * 1e3, 1)[0] if done > 2 else 0.0
@@ -236,7 +242,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="skip the tile-shape autotuner")
     ap.add_argument("--md", type=int, default=0, metavar="STEPS",
-                    help="instead: NVE velocity-Verlet run of STEPS steps (dt 0.5 fs, 300 K) through nq_step")
+                    help="instead: NVE velocity-Verlet run of STEPS steps (dt 0.5 fs) through nq_step")
+    ap.add_argument("--md-temp", type=float, default=300.0, help="initial temperature (K) of --md")
+    ap.add_argument("--md-energy-scale", type=float, default=1.0,
+                    help="factor on the model's energy scale for --md (random weights have no repulsive core)")
+    ap.add_argument("--md-skin", type=float, default=1.0, help="neighbour-list skin (A) for --md")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
     args = ap.parse_args()
