@@ -167,8 +167,9 @@ nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int
  * (not of nq_step's graph) is bracketed by HIP events recorded on the
  * context's stream. nq_timing_report synchronises the stream and writes a JSON
  * object {"n_edges": E, "kernels": [{"name", "count", "ms_total",
- * "flop_per_launch", "bytes_per_launch"}...]} (algorithmic FLOPs and bytes of
- * one launch at the last edge count) into buf[cap] (host), then clears the
+ * "flop_per_launch", "mfma_flop_per_launch", "bytes_per_launch"}...]}
+ * (algorithmic FLOPs, the part of them done on the matrix cores, and HBM bytes
+ * of one launch at the last edge count) into buf[cap] (host), then clears the
  * record. *len (host) receives the length; NQ_ERR_CAPACITY if buf is too
  * small. */
 nq_status nq_timing(nq_ctx* ctx, int enable);
