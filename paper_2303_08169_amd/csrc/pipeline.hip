@@ -106,37 +106,54 @@ __global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __rest
 
 // ------------------------------------------------------------------ environment sums
 // One wavefront per centre i; lane = (channel c, group g), group g owns the
-// components lm = g, g+G, ... of Gamma_i[lm][c].
-template <int NY>
+// components lm = g, g+G, ... of Gamma_i[lm][c] (G = 64 / C). The centre's edges
+// are taken four at a time with all their loads issued before the sums, and
+// components past NY read a valid one and are dropped, so no load sits behind
+// a lane-dependent branch.
+template <int NY, int C>
 __global__ __launch_bounds__(256) void k_env_fwd(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
                                                  const float* __restrict__ esrc, int lde,
-                                                 const float* __restrict__ geo, int C, float scale,
+                                                 const float* __restrict__ geo, float scale,
                                                  float* __restrict__ gam) {
+  constexpr int G = 64 / C, NQ = (NY + G - 1) / G, U = 4;
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= n) return;
   const int lane = threadIdx.x % 64;
-  const int c = lane % C, g = lane / C, G = 64 / C;
-  float acc[NY];
+  const int c = lane % C, g = lane / C;
+  int lmq[NQ], lq[NQ];
 #pragma unroll
-  for (int q = 0; q < NY; ++q) acc[q] = 0.f;
+  for (int q = 0; q < NQ; ++q) {
+    const int lm = min(g + q * G, NY - 1);
+    lmq[q] = lm;
+    lq[q] = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+  }
+  float acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
   const int ne = *nedge_p;
   const int b = min(eoff[i], ne), e1 = min(eoff[i + 1], ne);
-  for (int e = b; e < e1; ++e) {
-    const float* Y = geo + (int64_t)e * kGeo + kGeoY;
+  int e = b;
+  for (; e + U <= e1; e += U) {
+    float ev[U][NQ], yv[U][NQ];
 #pragma unroll
-    for (int q = 0; q < NY; ++q) {
-      const int lm = g + q * G;
-      if (lm < NY) {
-        const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
-        acc[q] += esrc[(int64_t)e * lde + l * C + c] * Y[lm];
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) {
+        ev[u][q] = esrc[(int64_t)(e + u) * lde + lq[q] * C + c];
+        yv[u][q] = geo[(int64_t)(e + u) * kGeo + kGeoY + lmq[q]];
       }
-    }
-  }
 #pragma unroll
-  for (int q = 0; q < NY; ++q) {
-    const int lm = g + q * G;
-    if (lm < NY) gam[(i * NY + lm) * C + c] = acc[q] * scale;
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] += ev[u][q] * yv[u][q];
   }
+  for (; e < e1; ++e)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q)
+      acc[q] += esrc[(int64_t)e * lde + lq[q] * C + c] * geo[(int64_t)e * kGeo + kGeoY + lmq[q]];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (g + q * G < NY) gam[(i * NY + g + q * G) * C + c] = acc[q] * scale;
 }
 
 // ------------------------------------------------------------------ group sums
@@ -764,31 +781,42 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Per-centre adjoint of the environment sum, part 1:
 // dGamma_i[lm][c] = nu^-1/2 sum_{j: (i,j) edge} ggc[(i,j)][lm][c]
-// (one wavefront per centre, lanes as in k_env_fwd).
-template <int NY>
+// (one wavefront per centre, lanes and edge batches as in k_env_fwd).
+template <int NY, int C>
 __global__ __launch_bounds__(256) void k_env_reduce(int64_t n, const int* __restrict__ nedge_p,
-                                                    const int* __restrict__ eoff, const float* __restrict__ ggc, int C,
+                                                    const int* __restrict__ eoff, const float* __restrict__ ggc,
                                                     float scale, float* __restrict__ ggam) {
+  constexpr int G = 64 / C, NQ = (NY + G - 1) / G, U = 4;
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= n) return;
   const int lane = threadIdx.x % 64;
-  const int c = lane % C, g = lane / C, G = 64 / C;
-  float acc[NY];
+  const int c = lane % C, g = lane / C;
+  int lmq[NQ];
 #pragma unroll
-  for (int q = 0; q < NY; ++q) acc[q] = 0.f;
+  for (int q = 0; q < NQ; ++q) lmq[q] = min(g + q * G, NY - 1);
+  float acc[NQ];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
   const int ne = *nedge_p;
   const int b = min(eoff[i], ne), e1 = min(eoff[i + 1], ne);
-  for (int e = b; e < e1; ++e)
+  int e = b;
+  for (; e + U <= e1; e += U) {
+    float v[U][NQ];
 #pragma unroll
-    for (int q = 0; q < NY; ++q) {
-      const int lm = g + q * G;
-      if (lm < NY) acc[q] += ggc[((int64_t)e * NY + lm) * C + c];
-    }
+    for (int u = 0; u < U; ++u)
 #pragma unroll
-  for (int q = 0; q < NY; ++q) {
-    const int lm = g + q * G;
-    if (lm < NY) ggam[(i * NY + lm) * C + c] = acc[q] * scale;
+      for (int q = 0; q < NQ; ++q) v[u][q] = ggc[((int64_t)(e + u) * NY + lmq[q]) * C + c];
+#pragma unroll
+    for (int u = 0; u < U; ++u)
+#pragma unroll
+      for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
   }
+  for (; e < e1; ++e)
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) acc[q] += ggc[((int64_t)e * NY + lmq[q]) * C + c];
+#pragma unroll
+  for (int q = 0; q < NQ; ++q)
+    if (g + q * G < NY) ggam[(i * NY + g + q * G) * C + c] = acc[q] * scale;
 }
 
 // Part 2, per (edge k, channel c) of centre i:
@@ -1034,6 +1062,19 @@ Epi e_add(float* o, int ld, int N) { return Epi{E_ADD, o, ld, N, nullptr, 0, nul
 
 unsigned grid_for(int64_t n, int per_block) { return (unsigned)std::max<int64_t>(1, cdiv(n, per_block)); }
 
+// Calls M(NY, C) with compile-time values for l <= 1 or 2 and C = 8 ... 64.
+#define NQ_DISPATCH_NY_C(NYV, CV, M)                                    \
+  do {                                                                  \
+    const int nq_c_ = (CV);                                             \
+    if ((NYV) == 4) {                                                   \
+      if (nq_c_ == 8) M(4, 8); else if (nq_c_ == 16) M(4, 16);          \
+      else if (nq_c_ == 32) M(4, 32); else M(4, 64);                    \
+    } else {                                                            \
+      if (nq_c_ == 8) M(9, 8); else if (nq_c_ == 16) M(9, 16);          \
+      else if (nq_c_ == 32) M(9, 32); else M(9, 64);                    \
+    }                                                                   \
+  } while (0)
+
 // ------------------------------------------------------------------ per-edge launches
 MixPtrs layer_mix(const nq_model* m, int t) {
   MixPtrs w{nullptr, nullptr, nullptr, nullptr, 0};
@@ -1143,12 +1184,10 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
   const float scale = (float)d.inv_sqrt_nu;
   // per edge: the dE/dGamma contributions; per atom: dE/dGamma written, offsets
   int sp = span_begin(ctx, "env_reduce" + std::to_string(t), 0, 4.0 * d.NY * d.C, 0, 4.0 * d.NY * d.C + 4.0);
-  if (d.L == 1)
-    k_env_reduce<4><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
-                                                              scale, ws.ggam);
-  else
-    k_env_reduce<9><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, d.C,
-                                                              scale, ws.ggam);
+#define NQ_ENVR(NYV, CV) \
+  k_env_reduce<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, scale, ws.ggam)
+  NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVR);
+#undef NQ_ENVR
   span_end(ctx, sp);
   // per edge: centre index, e, Y, dE/de written, dE/dY read-modify-write; per atom: dE/dGamma
   sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0, 4.0 + 8.0 * d.NW + 4.0 * d.NY + 8.0 * d.NY, 0,
@@ -1382,22 +1421,15 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
            "fwd.env" + std::to_string(t));
     const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
     const int lde = t == 1 ? 2 * d.NW : d.NW;
-    if (d.L == 1)
-      {
-        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t), 0, 4.0 * d.NW + 4.0 * d.NY, 0,
-                                   4.0 * d.NY * d.C + 4.0);
-        k_env_fwd<4><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
-                                                          ws.gam[t]);
-        span_end(ctx, sp_);
-      }
-    else
-      {
-        const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t), 0, 4.0 * d.NW + 4.0 * d.NY, 0,
-                                   4.0 * d.NY * d.C + 4.0);
-        k_env_fwd<9><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, d.C, inv_sqrt_nu,
-                                                          ws.gam[t]);
-        span_end(ctx, sp_);
-      }
+    {
+      const int sp_ = span_begin(ctx, "env_fwd" + std::to_string(t), 0, 4.0 * d.NW + 4.0 * d.NY, 0,
+                                 4.0 * d.NY * d.C + 4.0);
+#define NQ_ENVF(NYV, CV) \
+  k_env_fwd<NYV, CV><<<grid_for(n, 4), 256, 0, s>>>(n, ne, ws.v_eoff, esrc, lde, ws.geo, inv_sqrt_nu, ws.gam[t])
+      NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVF);
+#undef NQ_ENVF
+      span_end(ctx, sp_);
+    }
     launch_tp_fwd(ctx, m, t);
     NQ_HIP(hipGetLastError());
     // latent MLP on [x | s]; the last layer applies the residual update
