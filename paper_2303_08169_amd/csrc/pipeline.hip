@@ -473,18 +473,28 @@ struct TpFwdArgs {
   float* vout;
 };
 
-// T = C (V (x) Gamma_i) for one (edge, channel), path by path (zero
-// coefficients skipped at compile time): each component goes straight to the
-// edge's LDS rows Trow (stride CP), the scalar paths also to s.
-template <int LMAX>
-__device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, int c, float* Trow, int CP) {
-  constexpr int NY = TPSize<LMAX>::NY;
-  const float* Y = a.geo + e * kGeo + kGeoY;
+// Inputs of the forward product of one (edge, channel): V_{t-1} and Gamma_i.
+template <int LMAX> struct TpFwdIn {
+  static constexpr int NY = TPSize<LMAX>::NY;
   float V[NY], G[NY];
-  load_vprev<NY>(a.first, e, c, a.C, a.we1, a.ldwe, a.vprev, Y, V);
+};
+
+template <int LMAX>
+__device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int c, TpFwdIn<LMAX>& in) {
+  constexpr int NY = TPSize<LMAX>::NY;
+  load_vprev<NY>(a.first, e, c, a.C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
   const int64_t i = a.ei[e];
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) G[lm] = a.gam[(i * NY + lm) * a.C + c];
+  for (int lm = 0; lm < NY; ++lm) in.G[lm] = a.gam[(i * NY + lm) * a.C + c];
+}
+
+// T = C (V (x) Gamma_i) for one (edge, channel), path by path (zero
+// coefficients skipped at compile time): each component goes straight to the
+// edge's LDS rows Trow (stride CP; zero for a row past the last edge), the
+// scalar paths of a valid edge also to s.
+template <int LMAX>
+__device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, int c, float* Trow, int CP,
+                                   const TpFwdIn<LMAX>& in) {
   for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
     for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
@@ -494,10 +504,10 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, int c, float* 
 #pragma unroll
         for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
           const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
-          if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * G[l2 * l2 + m2];
+          if (cgv != 0.f) acc += cgv * in.V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
-      Trow[(toff + m3) * CP + c] = acc;
-      if (l3 == 0) a.s[e * a.lds + qs * a.C + c] = acc;
+      Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;
+      if (l3 == 0 && valid) a.s[e * a.lds + qs * a.C + c] = acc;
     }
   });
 }
@@ -521,15 +531,21 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   if constexpr (MW >= 0) {
     if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fT) : a.W.bT, a.W.n, lane);
   }
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
+  // Software pipeline over the workgroup's groups: the next group's inputs are
+  // loaded while this group is mixed. A row past the last edge reads the last
+  // edge and contributes zeros.
+  auto issue = [&](int64_t g, TpFwdIn<LMAX>& inr) {
+    const int64_t eg = g * epb + el;
+    tp_fwd_load<LMAX>(a, eg < ne ? eg : ne - 1, c, inr);
+  };
+  TpFwdIn<LMAX> in;
+  int64_t grp = blockIdx.x;
+  if (grp < ngroups) issue(grp, in);
+  for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
-    float* Trow = Tl + el * NT * CP;
-    if (e < ne) {
-      tp_fwd_edge<LMAX>(a, e, c, Trow, CP);
-    } else if (!a.last) {
-#pragma unroll
-      for (int k = 0; k < NT; ++k) Trow[k * CP + c] = 0.f;
-    }
+    tp_fwd_edge<LMAX>(a, e, e < ne, c, Tl + el * NT * CP, CP, in);
+    const int64_t nx = grp + gridDim.x;
+    issue(nx < ngroups ? nx : grp, in);
     if (a.last) continue;
     __syncthreads();
     if constexpr (MW >= 0)
@@ -736,17 +752,26 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   if constexpr (MW >= 0) {
     if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fN) : a.W.bN, a.W.n, lane);
   }
-  for (int64_t grp = blockIdx.x; grp < ngroups; grp += gridDim.x) {
-    const int64_t e = grp * epb + el;
-    const bool valid = e < ne;
-    const int64_t ec = valid ? e : ne - 1;  // loads of a row past the end read the last edge
-    float gv[NY];
+  // Software pipeline over the workgroup's groups: the loads of the next
+  // group (dE/dV_t and the adjoint's other inputs) are issued before this
+  // group's adjoint arithmetic, so their latency overlaps it. A row past the
+  // last edge reads the last edge.
+  float gv[NY];
+  TpBwdIn<LMAX> in;
+  auto issue = [&](int64_t g, float (&gvr)[NY], TpBwdIn<LMAX>& inr) {
+    const int64_t eg = g * epb + el;
+    const int64_t ec = eg < ne ? eg : ne - 1;
     if (!a.last) {
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gv[lm] = a.gvin[(ec * NY + lm) * C + c];
+      for (int lm = 0; lm < NY; ++lm) gvr[lm] = a.gvin[(ec * NY + lm) * C + c];
     }
-    TpBwdIn<LMAX> in;
-    tp_bwd_load<LMAX>(a, ec, c, in);
+    tp_bwd_load<LMAX>(a, ec, c, inr);
+  };
+  int64_t grp = blockIdx.x;
+  if (grp < ngroups) issue(grp, gv, in);
+  for (; grp < ngroups; grp += gridDim.x) {
+    const int64_t e = grp * epb + el;
+    const bool valid = e < ne;
     if (!a.last) {
       // The previous group's reads of gTl finished before this barrier pair
       // lets the mixing overwrite it.
@@ -759,7 +784,14 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
         mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, a.W);
       __syncthreads();
     }
+    float gvn[NY];
+    TpBwdIn<LMAX> inn;
+    const int64_t nx = grp + gridDim.x;
+    issue(nx < ngroups ? nx : grp, gvn, inn);
     if (valid) tp_bwd_edge<LMAX>(a, e, c, gTl + el * NT * CP, CP, in);
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
+    in = inn;
   }
 }
 
