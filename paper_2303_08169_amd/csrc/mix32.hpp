@@ -63,15 +63,27 @@ __device__ inline void load_frag(Frag<KIND>& f, const void* base, int64_t lo_off
   }
 }
 
-// acc += A (this lane's row, 32-deep slice starting at a) x fragment.
-// `a` points at the 32 consecutive K values of this lane's row (F32: values
-// a[4 j + lane/16]; BF16: a[8 (lane/16) .. +8]).
+// A fragment: this lane's row of a 32-deep slice (F32: values 4 j + lane/16;
+// BF16: values 8 (lane/16) .. +8, split into hi and lo for BF16X3).
+template <int KIND> struct AFrag;
+template <> struct AFrag<G_F32> {
+  float v[8];
+};
+template <> struct AFrag<G_BF16> {
+  bf16x8 h;
+};
+template <> struct AFrag<G_BF16X3> {
+  bf16x8 h, l;
+};
+
+// `a` points at the 32 consecutive K values of this lane's row; an invalid row
+// gives zeros.
 template <int KIND>
-__device__ inline floatx4 mma32(floatx4 acc, const float* a, bool valid, const Frag<KIND>& f, int lane) {
+__device__ inline AFrag<KIND> load_a(const float* a, bool valid, int lane) {
+  AFrag<KIND> A;
   if constexpr (KIND == G_F32) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j)
-      acc = __builtin_amdgcn_mfma_f32_16x16x4f32(valid ? a[4 * j + (lane >> 4)] : 0.f, f.b[j], acc, 0, 0, 0);
+    for (int j = 0; j < 8; ++j) A.v[j] = valid ? a[4 * j + (lane >> 4)] : 0.f;
   } else {
     float v[8] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
     if (valid) {
@@ -79,19 +91,34 @@ __device__ inline floatx4 mma32(floatx4 acc, const float* a, bool valid, const F
       *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(a + (lane >> 4) * 8 + 4);
     }
     if constexpr (KIND == G_BF16) {
-      bf16x8 h;
 #pragma unroll
-      for (int k = 0; k < 8; ++k) h[k] = (bf16)v[k];
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, f.hi, acc, 0, 0, 0);
+      for (int k = 0; k < 8; ++k) A.h[k] = (bf16)v[k];
     } else {
-      bf16x8 h, l;
-      split_bf16(v, h, l);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(l, f.hi, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, f.lo, acc, 0, 0, 0);
-      acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, f.hi, acc, 0, 0, 0);
+      split_bf16(v, A.h, A.l);
     }
   }
+  return A;
+}
+
+// acc += A x B for one 32-deep slice.
+template <int KIND>
+__device__ inline floatx4 mma_frag(floatx4 acc, const AFrag<KIND>& A, const Frag<KIND>& f) {
+  if constexpr (KIND == G_F32) {
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(A.v[j], f.b[j], acc, 0, 0, 0);
+  } else if constexpr (KIND == G_BF16) {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h, f.hi, acc, 0, 0, 0);
+  } else {
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.l, f.hi, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h, f.lo, acc, 0, 0, 0);
+    acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(A.h, f.hi, acc, 0, 0, 0);
+  }
   return acc;
+}
+
+template <int KIND>
+__device__ inline floatx4 mma32(floatx4 acc, const float* a, bool valid, const Frag<KIND>& f, int lane) {
+  return mma_frag<KIND>(acc, load_a<KIND>(a, valid, lane), f);
 }
 
 // Forward B fragments of wave W: for each owned tile (l3, ct) and K slice ks,
@@ -160,24 +187,41 @@ __device__ inline void mix_fwd(const FwdB<KIND, W>& B, const float* Tl, int64_t 
   }
 }
 
-// Adjoint mixing of one group: gV in LDS ([edge][NY][CP]) -> gT in LDS.
+constexpr bool bwd_has(int W, int l3) {
+  for (int j = 0; j < kBwdN[W]; ++j)
+    if (kBwd[W][j].l3 == l3) return true;
+  return false;
+}
+
+// Adjoint mixing of one group: gV in LDS ([edge][NY][CP]) -> gT in LDS. The
+// wave's column tiles of one l3 share their A fragments (rows (edge, m) of
+// dE/dV), so each row tile's fragment is loaded and split once.
 template <int KIND, int W>
 __device__ inline void mix_bwd(const BwdB<KIND, W>& B, const float* gVl, float* gTl, int lane) {
 #pragma unroll
-  for (int j = 0; j < kBwdN[W]; ++j) {
-    const int l3 = kBwd[W][j].l3, ct = kBwd[W][j].ct, nm = 2 * l3 + 1, R = EPB * nm;
-    const int n = 16 * ct + (lane & 15), p = n / C, c = n % C;
+  for (int l3 = 2; l3 >= 0; --l3) {
+    if (!bwd_has(W, l3)) continue;
+    const int nm = 2 * l3 + 1, R = EPB * nm;
 #pragma unroll
     for (int rt = 0; rt < RT[l3]; ++rt) {
       const int r = rt * 16 + (lane & 15);
       const bool rv = r < R;
       const int el = rv ? r / nm : 0, m = rv ? r % nm : 0;
-      const floatx4 acc =
-          mma32<KIND>(floatx4{0.f, 0.f, 0.f, 0.f}, gVl + (el * NY + l3 * l3 + m) * CP, rv, B.f[j], lane);
+      const AFrag<KIND> A = load_a<KIND>(gVl + (el * NY + l3 * l3 + m) * CP, rv, lane);
+      int dst[4];  // LDS row offsets of this lane's four output rows (-1: past the group)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int rr = rt * 16 + 4 * (lane >> 4) + q;
-        if (rr < R) gTl[((rr / nm) * NT + TOFF[l3][p] + rr % nm) * CP + c] = acc[q];
+        dst[q] = rr < R ? ((rr / nm) * NT + rr % nm) * CP : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kBwdN[W]; ++j) {
+        if (kBwd[W][j].l3 != l3) continue;
+        const int n = 16 * kBwd[W][j].ct + (lane & 15), p = n / C, c = n % C;
+        const floatx4 acc = mma_frag<KIND>(floatx4{0.f, 0.f, 0.f, 0.f}, A, B.f[j]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (dst[q] >= 0) gTl[dst[q] + TOFF[l3][p] * CP + c] = acc[q];
       }
     }
   }
