@@ -248,13 +248,16 @@ template <int LMAX> struct TPSize {
 template <int NY>
 __device__ inline void load_vprev(bool first, int64_t e, int c, int C, const float* we1, int ldwe,
                                   const float* vprev, const float* Y, float* V) {
+  // one 64-bit row address per source; the components are fixed offsets from it
+  const float* w = we1 + e * ldwe + c;
+  const float* v = vprev + e * (NY * C) + c;
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) {
     if (first) {
       const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
-      V[lm] = we1[e * ldwe + l * C + c] * Y[lm];
+      V[lm] = w[l * C] * Y[lm];
     } else {
-      V[lm] = vprev[(e * NY + lm) * C + c];
+      V[lm] = v[lm * C];
     }
   }
 }
@@ -479,22 +482,26 @@ template <int LMAX> struct TpFwdIn {
   float V[NY], G[NY];
 };
 
-template <int LMAX>
+template <int LMAX, int CC>
 __device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int c, TpFwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
-  load_vprev<NY>(a.first, e, c, a.C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
-  const int64_t i = a.ei[e];
+  const int C = CC > 0 ? CC : a.C;
+  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
+  const float* g = a.gam + (int64_t)a.ei[e] * (NY * C) + c;
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) in.G[lm] = a.gam[(i * NY + lm) * a.C + c];
+  for (int lm = 0; lm < NY; ++lm) in.G[lm] = g[lm * C];
 }
 
 // T = C (V (x) Gamma_i) for one (edge, channel), path by path (zero
 // coefficients skipped at compile time): each component goes straight to the
 // edge's LDS rows Trow (stride CP; zero for a row past the last edge), the
-// scalar paths of a valid edge also to s.
-template <int LMAX>
+// scalar paths of a valid edge also to s. CC: channel count if known at
+// compile time, else 0.
+template <int LMAX, int CC>
 __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, int c, float* Trow, int CP,
                                    const TpFwdIn<LMAX>& in) {
+  const int C = CC > 0 ? CC : a.C;
+  float* srow = a.s + e * a.lds + c;
   for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
     for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
@@ -507,7 +514,7 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, in
           if (cgv != 0.f) acc += cgv * in.V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
       Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;
-      if (l3 == 0 && valid) a.s[e * a.lds + qs * a.C + c] = acc;
+      if (l3 == 0 && valid) srow[qs * C] = acc;
     }
   });
 }
@@ -536,14 +543,14 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   // edge and contributes zeros.
   auto issue = [&](int64_t g, TpFwdIn<LMAX>& inr) {
     const int64_t eg = g * epb + el;
-    tp_fwd_load<LMAX>(a, eg < ne ? eg : ne - 1, c, inr);
+    tp_fwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, eg < ne ? eg : ne - 1, c, inr);
   };
   TpFwdIn<LMAX> in;
   int64_t grp = blockIdx.x;
   if (grp < ngroups) issue(grp, in);
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
-    tp_fwd_edge<LMAX>(a, e, e < ne, c, Tl + el * NT * CP, CP, in);
+    tp_fwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, e < ne, c, Tl + el * NT * CP, CP, in);
     const int64_t nx = grp + gridDim.x;
     issue(nx < ngroups ? nx : grp, in);
     if (a.last) continue;
@@ -663,28 +670,29 @@ template <int LMAX> struct TpBwdIn {
   float V[NY], G[NY], gs[NS];
 };
 
-template <int LMAX>
+template <int LMAX, int CC>
 __device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int c, TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
-  const int C = a.C;
+  const int C = CC > 0 ? CC : a.C;
   load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
-  const int64_t i = a.ei[e];
+  const float* g = a.gam + (int64_t)a.ei[e] * (NY * C) + c;
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) in.G[lm] = a.gam[(i * NY + lm) * C + c];
+  for (int lm = 0; lm < NY; ++lm) in.G[lm] = g[lm * C];
+  const float* gsr = a.gs + e * a.ldgs + c;
 #pragma unroll
-  for (int q = 0; q <= LMAX; ++q) in.gs[q] = a.gs[e * a.ldgs + q * C + c];
+  for (int q = 0; q <= LMAX; ++q) in.gs[q] = gsr[q * C];
 }
 
 // Adjoint of the tensor product of one (edge, channel), given dE/dT from the
 // mixing adjoint (gTrow: this edge's rows in LDS, unused for the last layer)
 // and dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i,
 // and either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
-// the w0 part of dE/dY into gY.
-template <int LMAX>
+// the w0 part of dE/dY into gY. CC: channel count if known at compile time.
+template <int LMAX, int CC>
 __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP,
                                    const TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
-  const int C = a.C;
+  const int C = CC > 0 ? CC : a.C;
   float gV[NY], gG[NY];
 #pragma unroll
   for (int k = 0; k < NY; ++k) {
@@ -709,28 +717,33 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
         }
     }
   });
+  float* ggr = a.ggc + e * (NY * C) + c;
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) a.ggc[(e * NY + lm) * C + c] = gG[lm];
+  for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = gG[lm];
   if (!a.first) {
+    float* gvr = a.gvout + e * (NY * C) + c;
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) a.gvout[(e * NY + lm) * C + c] = gV[lm];
+    for (int lm = 0; lm < NY; ++lm) gvr[lm * C] = gV[lm];
   } else {
     // V0[c][lm] = w0[l][c] Y[lm]. The channel sums for dE/dY reduce each
     // component right away: gathering all of them first for add_group_sums
     // raises the register peak of the 32-channel kernel into spills.
     const float* Y = a.geo + e * kGeo + kGeoY;
+    const float* w0r = a.we1 + e * a.ldwe + c;
+    float* gwr = a.gew + e * a.ldgew + c;
+    float* gYr = a.gY + e * 16;
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       float gw = 0.f;
-      const float w0 = a.we1[e * a.ldwe + l * C + c];
+      const float w0 = w0r[l * C];
 #pragma unroll
       for (int m = 0; m < 2 * l + 1; ++m) {
         gw += gV[l * l + m] * Y[l * l + m];
         float part = w0 * gV[l * l + m];
         for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-        if (c == 0) a.gY[e * 16 + l * l + m] += part;
+        if (c == 0) gYr[l * l + m] += part;
       }
-      a.gew[e * a.ldgew + l * C + c] = gw;
+      gwr[l * C] = gw;
     }
   }
 }
@@ -762,10 +775,11 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     const int64_t eg = g * epb + el;
     const int64_t ec = eg < ne ? eg : ne - 1;
     if (!a.last) {
+      const float* src = a.gvin + ec * (NY * C) + c;
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gvr[lm] = a.gvin[(ec * NY + lm) * C + c];
+      for (int lm = 0; lm < NY; ++lm) gvr[lm] = src[lm * C];
     }
-    tp_bwd_load<LMAX>(a, ec, c, inr);
+    tp_bwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, ec, c, inr);
   };
   int64_t grp = blockIdx.x;
   if (grp < ngroups) issue(grp, gv, in);
@@ -788,7 +802,7 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     TpBwdIn<LMAX> inn;
     const int64_t nx = grp + gridDim.x;
     issue(nx < ngroups ? nx : grp, gvn, inn);
-    if (valid) tp_bwd_edge<LMAX>(a, e, c, gTl + el * NT * CP, CP, in);
+    if (valid) tp_bwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, c, gTl + el * NT * CP, CP, in);
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
     in = inn;
