@@ -114,6 +114,32 @@ nq_status nq_energy_forces(nq_ctx* ctx, const nq_model* model, const double* pos
                            const int32_t* species, int64_t n, const double cell[3], double* energy,
                            double* forces, double* atom_energy);
 
+/* Energies and forces of n_rep independent replicas (ring-polymer beads of
+ * the path-integral application, Sec. 4) of an n-atom system in the same box,
+ * in one evaluation: pos[n_rep*n*3] (device, FP64, replica-major), species
+ * [n_rep*n] (device, int32), energy[n_rep] (device, FP64: E of each replica),
+ * forces[n_rep*n*3] (device, FP64), atom_energy[n_rep*n] (device, FP64, or
+ * NULL). Only atoms of the same replica interact; each replica's results are
+ * those nq_energy_forces gives for it alone. The neighbour list covers all
+ * replicas (rebuilt as in nq_energy_forces). NQ_ERR_ARG for n_rep outside
+ * [1, 65536] or n * n_rep outside [2, 2^30). Asynchronous. */
+nq_status nq_energy_forces_replicas(nq_ctx* ctx, const nq_model* model, const double* pos,
+                                    const int32_t* species, int64_t n, int64_t n_rep,
+                                    const double cell[3], double* energy, double* forces,
+                                    double* atom_energy);
+
+/* Harmonic ring-polymer coupling of the n_rep beads of every atom (the
+ * path-integral replicas of Sec. 4; primitive discretisation):
+ *   E = 1/2 sum_a m_a w_P^2 sum_k |r_{k+1,a} - r_{k,a}|^2 (bead n_rep = bead 0),
+ *   w_P = n_rep k_B T / hbar, bead separations by minimum image.
+ * pos[n_rep*n*3] (device, FP64, bead-major), inv_mass[n] (device, FP64,
+ * 1/amu, shared by the beads), temperature in K. The spring forces are ADDED
+ * to forces[n_rep*n*3] (device, FP64, eV/A); energy[1] (device, FP64)
+ * receives E in eV. n_rep = 1 adds nothing. Asynchronous. */
+nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n,
+                          int64_t n_rep, const double cell[3], double temperature, double* forces,
+                          double* energy);
+
 /* n_steps velocity-Verlet steps (Eq. 1) of length dt_fs: v += dt/2 F/m;
  * r += dt v (wrapped into the box); F = F(r); v += dt/2 F/m. pos[n*3], vel[n*3]
  * (device, FP64, A and A/fs) are updated in place; inv_mass[n] (device, FP64,

@@ -102,9 +102,9 @@ void check_flags(nq_ctx* ctx) {
 }
 
 void neighbor_build_sync(nq_ctx* ctx, const double* pos, int64_t n, const double cell[3], double r_cut,
-                         double skin) {
+                         double skin, int64_t n_rep = 1) {
   NQ_HIP(hipSetDevice(ctx->device));
-  nbr_configure(ctx, n, cell, r_cut, skin);
+  nbr_configure(ctx, n, cell, r_cut, skin, n_rep);
   NbrList& nl = ctx->nl;
   for (int attempt = 0;; ++attempt) {
     zero_flags(ctx);
@@ -140,12 +140,14 @@ double default_skin(const double cell[3], double rc) {
 }
 
 // Make sure a neighbour list valid for this model exists and the workspace fits it.
-void ensure_list(nq_ctx* ctx, const nq_model* m, const double* pos, int64_t n, const double cell[3]) {
+// n counts the atoms of all n_rep replicas.
+void ensure_list(nq_ctx* ctx, const nq_model* m, const double* pos, int64_t n, const double cell[3],
+                 int64_t n_rep = 1) {
   NbrList& nl = ctx->nl;
   const double rc = m->dims.rc;
-  const bool ok = nl.built && nl.n == n && nl.box[0] == cell[0] && nl.box[1] == cell[1] && nl.box[2] == cell[2] &&
-                  nl.r_cut + nl.skin >= rc;
-  if (!ok) neighbor_build_sync(ctx, pos, n, cell, rc, default_skin(cell, rc));
+  const bool ok = nl.built && nl.n == n && nl.n_rep == n_rep && nl.box[0] == cell[0] && nl.box[1] == cell[1] &&
+                  nl.box[2] == cell[2] && nl.r_cut + nl.skin >= rc;
+  if (!ok) neighbor_build_sync(ctx, pos, n, cell, rc, default_skin(cell, rc), n_rep);
   const int64_t cap = rup((int64_t)(1.25 * (double)nl.n_entries) + 1024, 128);
   ws_ensure(ctx, m, cap, n);
 }
@@ -159,7 +161,7 @@ void check_common(nq_ctx* ctx, const nq_model* m, const double* pos, const int32
 }
 
 void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int32_t* species, int64_t n,
-                    double* energy, double* forces, double* atom_energy) {
+                    double* energy, double* forces, double* atom_energy, int64_t n_rep = 1) {
   NbrList& nl = ctx->nl;
   const double half = 0.5 * (nl.r_cut + nl.skin - m->dims.rc);
   int sp = span_begin(ctx, "neighbor_check_rebuild");
@@ -174,7 +176,7 @@ void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int
     forward_async(ctx, m, species, atom_energy);
     backward_async(ctx, m);
   }
-  finish_async(ctx, m, energy, forces);
+  finish_async(ctx, m, energy, forces, n_rep);
 }
 
 }  // namespace
@@ -280,6 +282,38 @@ nq_status nq_energy_forces(nq_ctx* ctx, const nq_model* model, const double* pos
     NQ_HIP(hipSetDevice(ctx->device));
     ensure_list(ctx, model, pos, n, cell);
     evaluate_async(ctx, model, pos, species, n, energy, forces, atom_energy);
+  });
+}
+
+nq_status nq_energy_forces_replicas(nq_ctx* ctx, const nq_model* model, const double* pos,
+                                    const int32_t* species, int64_t n, int64_t n_rep, const double cell[3],
+                                    double* energy, double* forces, double* atom_energy) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(n_rep >= 1 && n_rep <= 65536, NQ_ERR_ARG, "n_rep out of range");
+    NQ_REQUIRE(n >= 2 && n < ((int64_t)1 << 30) && n * n_rep < ((int64_t)1 << 30), NQ_ERR_ARG,
+               "n out of range");
+    check_common(ctx, model, pos, species, n * n_rep, cell);
+    NQ_REQUIRE(energy && forces, NQ_ERR_ARG, "null output");
+    NQ_HIP(hipSetDevice(ctx->device));
+    ensure_list(ctx, model, pos, n * n_rep, cell, n_rep);
+    evaluate_async(ctx, model, pos, species, n * n_rep, energy, forces, atom_energy, n_rep);
+  });
+}
+
+nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n, int64_t n_rep,
+                          const double cell[3], double temperature, double* forces, double* energy) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && pos && inv_mass && cell && forces && energy, NQ_ERR_ARG, "null argument");
+    NQ_REQUIRE(n >= 1 && n_rep >= 1 && n * n_rep < ((int64_t)1 << 30), NQ_ERR_ARG, "n or n_rep out of range");
+    NQ_REQUIRE(std::isfinite(temperature) && temperature >= 0, NQ_ERR_ARG, "bad temperature");
+    for (int k = 0; k < 3; ++k) NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0, NQ_ERR_ARG, "bad cell");
+    NQ_HIP(hipSetDevice(ctx->device));
+    // w_P = P k_B T / hbar (1/fs): k_B in eV/K, hbar in eV fs (CODATA 2018)
+    const double omega_p = (double)n_rep * 8.617333262e-5 * temperature / 0.6582119569;
+    ctx->rp_scratch.ensure((size_t)(n * n_rep) * sizeof(double));
+    ring_polymer_async(ctx->stream, pos, inv_mass, n, n_rep, omega_p, cell, forces, ctx->rp_scratch.as<double>(),
+                       energy);
+    NQ_HIP(hipGetLastError());
   });
 }
 

@@ -69,6 +69,58 @@ __global__ void k_record(const double* __restrict__ epot_now, const double* __re
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+__device__ inline double mic(double d, double L) { return d - L * rint(d / L); }
+
+// Harmonic coupling of the R beads (replicas) of every atom into a ring
+// (the path-integral ring polymer of the application in paper Sec. 4):
+//   E = 1/2 sum_a m_a w^2 sum_k |r_{k+1,a} - r_{k,a}|^2,  bead R = bead 0,
+//   F_{k,a} += m_a w^2 ((r_{k-1,a} - r_{k,a}) + (r_{k+1,a} - r_{k,a})),
+// bead separations by minimum image. One thread per (bead, atom); e_bond gets
+// the (k, k+1) bond energy of each thread.
+__global__ void k_ring_polymer(const double* __restrict__ pos, const double* __restrict__ inv_mass, int64_t n,
+                               int64_t R, double w2, double Lx, double Ly, double Lz,
+                               double* __restrict__ forces, double* __restrict__ e_bond) {
+  const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= n * R) return;
+  const int64_t k = idx / n, a = idx % n;
+  const int64_t prev = ((k + R - 1) % R) * n + a, next = ((k + 1) % R) * n + a;
+  const double kappa = w2 / inv_mass[a] * kEvPerAmuA2fs2;  // eV / A^2
+  const double L[3] = {Lx, Ly, Lz};
+  double e = 0.0;
+  for (int c = 0; c < 3; ++c) {
+    const double x = pos[3 * idx + c];
+    const double dp = mic(pos[3 * prev + c] - x, L[c]), dn = mic(pos[3 * next + c] - x, L[c]);
+    forces[3 * idx + c] += kappa * (dp + dn);
+    e += dn * dn;
+  }
+  e_bond[idx] = 0.5 * kappa * e;
+}
+
+// Neumaier-compensated FP64 sum of n values by one block.
+__global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ v, int64_t n, double* __restrict__ out) {
+  __shared__ double hs[1024], hc[1024];
+  double s = 0.0, c = 0.0;
+  for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
+    const double x = v[k];
+    const double t = s + x;
+    c += (fabs(s) >= fabs(x)) ? (s - t) + x : (x - t) + s;
+    s = t;
+  }
+  hs[threadIdx.x] = s;
+  hc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      const double a = hs[threadIdx.x], b = hs[threadIdx.x + o];
+      const double t = a + b;
+      hc[threadIdx.x] += hc[threadIdx.x + o] + ((fabs(a) >= fabs(b)) ? (a - t) + b : (b - t) + a);
+      hs[threadIdx.x] = t;
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = hs[0] + hc[0];
+}
+
 }  // namespace
 
 void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass, int64_t n,
@@ -90,5 +142,12 @@ void md_record_async(hipStream_t s, const double* epot_now, const double* ekin_n
 }
 
 void md_set_int_async(hipStream_t s, int* p, int v) { k_set_int<<<1, 1, 0, s>>>(p, v); }
+
+void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass, int64_t n, int64_t R,
+                        double omega_p, const double box[3], double* forces, double* e_bond, double* energy) {
+  k_ring_polymer<<<(unsigned)cdiv(n * R, 256), 256, 0, s>>>(pos, inv_mass, n, R, omega_p * omega_p, box[0], box[1],
+                                                           box[2], forces, e_bond);
+  k_sum<<<1, 1024, 0, s>>>(e_bond, n * R, energy);
+}
 
 }  // namespace nq

@@ -9,6 +9,10 @@
 // the skin list to the directed edges with d < r_c (edges sorted by (i, j)),
 // and finds for every edge (i, j) the slot of its reverse (j, i) by binary
 // search, which lets the force assembly gather instead of scatter.
+//
+// Several independent replicas of one box (ring-polymer beads) can share one
+// list: atom a belongs to replica a / n_per, every replica has its own cell
+// grid, and only atoms of the same replica are neighbours.
 #include <cmath>
 
 #include "nq_internal.hpp"
@@ -26,6 +30,8 @@ struct CellGeom {
   int nc[3];
   int noff[3];
   int off[3][3];
+  int ncell;      // cells of one replica
+  int64_t n_per;  // atoms of one replica
 };
 
 __device__ inline double mic1(double d, double L) { return d - L * rint(d / L); }
@@ -67,7 +73,7 @@ __global__ void k_bin(const double* __restrict__ pos, int64_t n, CellGeom g, int
     int ci = (int)(x * g.inv_cell[k]);
     c[k] = ci < 0 ? 0 : (ci >= g.nc[k] ? g.nc[k] - 1 : ci);
   }
-  int cell = (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
+  const int cell = (int)(a / g.n_per) * g.ncell + (c[2] * g.nc[1] + c[1]) * g.nc[0] + c[0];
   atom_cell[a] = cell;
   atomicAdd(&cell_count[cell], 1);
 }
@@ -122,7 +128,8 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_rows(
   if (a >= n) return;
   int* row = rowbuf + w * k_max;
   const double ax = pos[3 * a], ay = pos[3 * a + 1], az = pos[3 * a + 2];
-  const int cell = atom_cell[a];
+  const int rep0 = atom_cell[a] / g.ncell * g.ncell;  // first cell of this atom's replica
+  const int cell = atom_cell[a] - rep0;
   const int cx = cell % g.nc[0], cy = (cell / g.nc[0]) % g.nc[1], cz = cell / (g.nc[0] * g.nc[1]);
   int cnt = 0;
   for (int oz = 0; oz < g.noff[2]; ++oz)
@@ -131,7 +138,7 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_rows(
         int x = (cx + g.off[0][ox] + g.nc[0]) % g.nc[0];
         int y = (cy + g.off[1][oy] + g.nc[1]) % g.nc[1];
         int z = (cz + g.off[2][oz] + g.nc[2]) % g.nc[2];
-        int c = (z * g.nc[1] + y) * g.nc[0] + x;
+        int c = rep0 + (z * g.nc[1] + y) * g.nc[0] + x;
         int s = cell_start[c], e = cell_start[c + 1];
         for (int base = s; base < e; base += kWave) {
           int idx = base + lane;
@@ -284,23 +291,27 @@ CellGeom make_geom(const NbrList& nl) {
       g.off[k][0] = 0;
     }
   }
+  g.ncell = nl.nc[0] * nl.nc[1] * nl.nc[2];
+  g.n_per = nl.n / nl.n_rep;
   return g;
 }
 
 }  // namespace
 
-void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin) {
+void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin, int64_t n_rep) {
   NbrList& nl = ctx->nl;
+  NQ_REQUIRE(n_rep >= 1 && n % n_rep == 0 && n / n_rep > 1, NQ_ERR_ARG, "replicas must split the atoms evenly");
   const double rl = r_cut + skin;
   for (int k = 0; k < 3; ++k)
     NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0 && rl < 0.5 * cell[k], NQ_ERR_ARG,
                "r_cut + skin must be below half of every box length (minimum image)");
   NQ_REQUIRE(r_cut > 0 && skin >= 0, NQ_ERR_ARG, "bad r_cut or skin");
   NQ_REQUIRE(n > 1 && n < (int64_t)1 << 30, NQ_ERR_ARG, "n out of range");
-  const bool same = nl.n == n && nl.box[0] == cell[0] && nl.box[1] == cell[1] && nl.box[2] == cell[2] &&
-                    nl.r_cut == r_cut && nl.skin == skin;
+  const bool same = nl.n == n && nl.n_rep == n_rep && nl.box[0] == cell[0] && nl.box[1] == cell[1] &&
+                    nl.box[2] == cell[2] && nl.r_cut == r_cut && nl.skin == skin;
   if (same && nl.k_max > 0) return;
   nl.n = n;
+  nl.n_rep = n_rep;
   for (int k = 0; k < 3; ++k) {
     nl.box[k] = cell[k];
     nl.nc[k] = std::max(1, (int)std::floor(cell[k] / rl));
@@ -308,11 +319,12 @@ void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, d
   nl.r_cut = r_cut;
   nl.skin = skin;
   const double vol = cell[0] * cell[1] * cell[2];
-  const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * (double)n / vol;
+  const double expect = 4.0 / 3.0 * M_PI * rl * rl * rl * (double)(n / n_rep) / vol;
   int kmax = (int)rup((int64_t)(1.5 * expect + 32), 32);
-  nl.k_max = (int)std::min<int64_t>(kmax, rup(n, 32));
+  nl.k_max = (int)std::min<int64_t>(kmax, rup(n / n_rep, 32));
   nl.built = false;
-  const int64_t ncell = (int64_t)nl.nc[0] * nl.nc[1] * nl.nc[2];
+  const int64_t ncell = (int64_t)nl.nc[0] * nl.nc[1] * nl.nc[2] * n_rep;
+  NQ_REQUIRE(ncell < ((int64_t)1 << 30), NQ_ERR_ARG, "too many cells");
   nl.cell_count.ensure(ncell * 4);
   nl.cell_start.ensure((ncell + 1) * 4);
   nl.cell_fill.ensure(ncell * 4);
@@ -329,7 +341,7 @@ void nbr_build_async(nq_ctx* ctx, const double* pos, bool predicated) {
   NbrList& nl = ctx->nl;
   NQ_REQUIRE(nl.k_max > 0 && nl.k_max <= 2048, NQ_ERR_CAPACITY, "neighbour row capacity out of range");
   const CellGeom g = make_geom(nl);
-  const int64_t ncell = (int64_t)nl.nc[0] * nl.nc[1] * nl.nc[2];
+  const int64_t ncell = (int64_t)g.ncell * nl.n_rep;
   const int64_t n = nl.n;
   hipStream_t s = ctx->stream;
   int* flags = nl.flags.as<int>();

@@ -123,7 +123,8 @@ struct nq_model {
 namespace nq {
 
 struct NbrList {
-  int64_t n = 0;
+  int64_t n = 0;          // atoms of all replicas
+  int64_t n_rep = 1;      // independent replicas (same box), n / n_rep atoms each
   double box[3] = {0, 0, 0};
   double r_cut = 0, skin = 0;
   int nc[3] = {0, 0, 0};
@@ -192,6 +193,7 @@ struct nq_ctx {
   hipGraphExec_t graph_exec = nullptr;
   std::vector<const void*> graph_key;
   nq::DevBuf md_scratch;
+  nq::DevBuf rp_scratch;  // ring-polymer bond energies
   int64_t last_edges = 0;
   int64_t ws_budget = (int64_t)160 << 30;  // bytes allowed for per-edge activations
   // per-launch timing with HIP events on the context's stream
@@ -205,7 +207,7 @@ struct nq_ctx {
 namespace nq {
 
 // ---- neighbour list (neighbor.hip)
-void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin);
+void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin, int64_t n_rep = 1);
 void nbr_build_async(nq_ctx* ctx, const double* pos, bool predicated);
 void nbr_displacement_check_async(nq_ctx* ctx, const double* pos, double half_margin);
 void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut);
@@ -221,7 +223,7 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
 void chunk_view_async(nq_ctx* ctx, int chunk);
 void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy);
 void backward_async(nq_ctx* ctx, const nq_model* m);
-void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces);
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep = 1);
 
 int gemm_variant_count(int prec, int NP);
 
@@ -230,6 +232,10 @@ void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const 
                         int64_t n, double half_dt);
 void md_drift_async(hipStream_t s, double* pos, const double* vel, int64_t n, double dt,
                     const double box[3]);
+// Ring-polymer springs of R beads x n atoms: forces += spring forces (eV/A),
+// energy[0] = spring energy (eV); e_bond: n R doubles of scratch.
+void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass, int64_t n, int64_t R,
+                        double omega_p, const double box[3], double* forces, double* e_bond, double* energy);
 void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n,
                    double* out);
 

@@ -609,11 +609,14 @@ __global__ void k_atom_energy(int64_t n, const int* __restrict__ nedge_p, const 
   if (out) out[a] = s;
 }
 
-// Neumaier-compensated FP64 sum of n values by one block.
+// Neumaier-compensated FP64 sums of consecutive segments of n values, one
+// block per segment (one segment per replica): energy[b] = sum of v[b n, (b+1) n).
 __global__ __launch_bounds__(1024) void k_total_energy(int64_t n, const double* __restrict__ v,
                                                        double* __restrict__ energy) {
   __shared__ double hs[1024], hc[1024];
   double s = 0.0, c = 0.0;
+  v += (int64_t)blockIdx.x * n;
+  energy += blockIdx.x;
   for (int64_t k = threadIdx.x; k < n; k += blockDim.x) {
     const double x = v[k];
     const double t = s + x;
@@ -1598,12 +1601,12 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
 }
 
 // Whole-system totals after every chunk: compensated energy and force gather.
-void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces) {
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep) {
   Workspace& ws = ctx->ws;
   hipStream_t s = ctx->stream;
   const int64_t n = ws.n_atoms;
   int sp = span_begin(ctx, "total_energy");
-  k_total_energy<<<1, 1024, 0, s>>>(n, ws.atomE, energy);
+  k_total_energy<<<(unsigned)n_rep, 1024, 0, s>>>(n / n_rep, ws.atomE, energy);
   span_end(ctx, sp);
   sp = span_begin(ctx, "forces");
   k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ws.nedge.as<int>(), ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr,

@@ -100,6 +100,35 @@ class Potential:
                                           _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
         return (E, F, Ei) if atom_energy else (E, F)
 
+    def energy_forces_replicas(self, pos, species, box, atom_energy=False):
+        """Replicas of one box in one evaluation: pos [R, n, 3] f64, species
+        [R, n] int32 -> (E [R] f64, F [R, n, 3] f64[, E_i [R, n] f64])."""
+        if pos.dim() != 3 or pos.shape[2] != 3 or species.shape != pos.shape[:2]:
+            raise ValueError("positions [R, n, 3], species [R, n]")
+        R, n = pos.shape[0], pos.shape[1]
+        self._check_inputs(pos.reshape(R * n, 3), species.reshape(R * n))
+        F = torch.empty_like(pos)
+        E = torch.empty(R, dtype=torch.float64, device=self.device)
+        Ei = torch.empty((R, n), dtype=torch.float64, device=self.device) if atom_energy else None
+        self._sync_stream()
+        B.check(self.lib.nq_energy_forces_replicas(self._ctx, self._model, _ptr(pos), _ptr(species), n, R,
+                                                   _cell(box), _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
+        return (E, F, Ei) if atom_energy else (E, F)
+
+    def ring_polymer(self, pos, inv_mass, box, temperature, forces, energy=None):
+        """Adds the ring-polymer spring forces of the beads pos [R, n, 3] to
+        forces [R, n, 3] and returns the spring energy [1] (eV)."""
+        if pos.dim() != 3 or forces.shape != pos.shape or inv_mass.shape != (pos.shape[1],):
+            raise ValueError("positions and forces [R, n, 3], inv_mass [n]")
+        for t in (pos, inv_mass, forces):
+            if t.device != self.device or t.dtype != torch.float64 or not t.is_contiguous():
+                raise TypeError("ring-polymer arrays must be contiguous float64 on the potential's device")
+        E = energy if energy is not None else torch.empty(1, dtype=torch.float64, device=self.device)
+        self._sync_stream()
+        B.check(self.lib.nq_ring_polymer(self._ctx, _ptr(pos), _ptr(inv_mass), pos.shape[1], pos.shape[0],
+                                         _cell(box), float(temperature), _ptr(forces), _ptr(E)), self._ctx)
+        return E
+
     def step(self, pos, vel, inv_mass, species, box, dt_fs, n_steps, forces, epot=None, ekin=None):
         """n_steps velocity-Verlet steps in place; forces must hold F(pos) on entry."""
         self._check_inputs(pos, species)
