@@ -230,6 +230,56 @@ def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
     pot.close()
 
 
+def replicas_run(args, cf, pos, z, box, temperature=300.0):
+    """Path-integral workload: args.replicas perturbed replicas (beads) of the
+    system evaluated in one nq_energy_forces_replicas call plus the ring-polymer
+    springs, against the same replicas evaluated one call each."""
+    import numpy as np
+    import torch
+
+    from paper_2303_08169_amd import binding as B
+    from paper_2303_08169_amd.potential import Potential
+    from synth import weight_blob
+    from synth.nh3 import masses
+
+    R = args.replicas
+    segs, _ = B.weight_layout(B.make_desc(cf.model, args.precision))
+    w = weight_blob(cf.weight_seed, segs)
+    pot = Potential(cf.model, w, args.precision)
+    rng = np.random.default_rng(400)
+    reps = np.stack([(pos + rng.normal(scale=0.02, size=pos.shape)) % box for _ in range(R)])
+    dev = torch.device("cuda", 0)
+    P = torch.tensor(reps, device=dev)
+    Z = torch.tensor(np.tile(z, (R, 1)), dtype=torch.int32, device=dev)
+    IM = torch.tensor(1.0 / masses(z), device=dev)
+
+    def batched():
+        E, F = pot.energy_forces_replicas(P, Z, box)
+        return pot.ring_polymer(P, IM, box, temperature, F)
+
+    singles = [(P[r].contiguous(), Z[r].contiguous()) for r in range(R)]
+
+    def one_by_one():
+        for p_, z_ in singles:
+            pot.energy_forces(p_, z_, box)
+
+    out = {"metric": "atom-steps/s (E+F of all replicas + ring-polymer springs)", "workload": args.workload,
+           "replicas": R, "atoms_per_replica": cf.n_atoms, "precision": args.precision, "data": "synthetic"}
+    for name, fn in (("batched", batched), ("one_call_per_replica", one_by_one)):
+        for _ in range(args.warmup):
+            fn()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            fn()
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / args.steps
+        out[name] = {"ms_per_step": dt * 1e3, "atom_steps_per_s": R * cf.n_atoms / dt}
+        log(f"{name}: {dt * 1e3:.3f} ms per step of {R} replicas")
+    print(json.dumps(out), flush=True)
+    pot.close()
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -247,6 +297,8 @@ def main():
     ap.add_argument("--md-energy-scale", type=float, default=1.0,
                     help="factor on the model's energy scale for --md (random weights have no repulsive core)")
     ap.add_argument("--md-skin", type=float, default=1.0, help="neighbour-list skin (A) for --md")
+    ap.add_argument("--replicas", type=int, default=0, metavar="R",
+                    help="instead: R path-integral replicas of the workload in one call (with ring-polymer springs)")
     ap.add_argument("--copy-calib", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -275,6 +327,8 @@ def main():
     pos, z, box = make_system(cf.n_atoms, cf.seed)
     if args.md:
         return md_run(args, cf, pos, z, box)
+    if args.replicas:
+        return replicas_run(args, cf, pos, z, box)
     desc = B.make_desc(cf.model, args.precision)
     segs, _ = B.weight_layout(desc)
     w = weight_blob(cf.weight_seed, segs)
