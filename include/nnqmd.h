@@ -128,6 +128,21 @@ nq_status nq_energy_forces_replicas(nq_ctx* ctx, const nq_model* model, const do
                                     const double cell[3], double* energy, double* forces,
                                     double* atom_energy);
 
+/* One GPU's share of a spatial decomposition (Sec. 2.4): n_local atoms owned
+ * by this domain followed by n_total - n_local ghost atoms (copies of
+ * neighbouring domains' atoms within the cutoff). pos[n_total*3] (device,
+ * FP64), species[n_total] (device, int32). Only local atoms are centres:
+ * energy[1] (device, FP64) = sum of E_i over the local atoms, atom_energy
+ * [n_total] (device, FP64, or NULL) is 0 for ghosts, and forces[n_total*3]
+ * (device, FP64) holds -dE/dr of this domain's energy for local AND ghost atoms
+ * (the ghost rows are what a reverse exchange adds to the owners). The cell
+ * must enclose all atoms with at least r_c + skin of empty space around them,
+ * so that no periodic image is within reach. Asynchronous. */
+nq_status nq_energy_forces_domain(nq_ctx* ctx, const nq_model* model, const double* pos,
+                                  const int32_t* species, int64_t n_local, int64_t n_total,
+                                  const double cell[3], double* energy, double* forces,
+                                  double* atom_energy);
+
 /* Harmonic ring-polymer coupling of the n_rep beads of every atom (the
  * path-integral replicas of Sec. 4; primitive discretisation):
  *   E = 1/2 sum_a m_a w_P^2 sum_k |r_{k+1,a} - r_{k,a}|^2 (bead n_rep = bead 0),

@@ -160,8 +160,10 @@ void check_common(nq_ctx* ctx, const nq_model* m, const double* pos, const int32
   for (int k = 0; k < 3; ++k) NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0, NQ_ERR_ARG, "bad cell");
 }
 
+// n_centres: atoms whose edges are evaluated (the others are ghosts), -1 = all.
 void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int32_t* species, int64_t n,
-                    double* energy, double* forces, double* atom_energy, int64_t n_rep = 1) {
+                    double* energy, double* forces, double* atom_energy, int64_t n_rep = 1,
+                    int64_t n_centres = -1) {
   NbrList& nl = ctx->nl;
   const double half = 0.5 * (nl.r_cut + nl.skin - m->dims.rc);
   int sp = span_begin(ctx, "neighbor_check_rebuild");
@@ -169,14 +171,14 @@ void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int
   nbr_build_async(ctx, pos, true);
   span_end(ctx, sp);
   sp = span_begin(ctx, "edge_list");
-  edges_build_async(ctx, pos, m->dims.rc);
+  edges_build_async(ctx, pos, m->dims.rc, n_centres);
   span_end(ctx, sp);
   for (int c = 0; c + 1 < (int)ctx->ws.chunks.size(); ++c) {
     chunk_view_async(ctx, c);
     forward_async(ctx, m, species, atom_energy);
     backward_async(ctx, m);
   }
-  finish_async(ctx, m, energy, forces, n_rep);
+  finish_async(ctx, m, energy, forces, n_rep, n_centres);
 }
 
 }  // namespace
@@ -297,6 +299,19 @@ nq_status nq_energy_forces_replicas(nq_ctx* ctx, const nq_model* model, const do
     NQ_HIP(hipSetDevice(ctx->device));
     ensure_list(ctx, model, pos, n * n_rep, cell, n_rep);
     evaluate_async(ctx, model, pos, species, n * n_rep, energy, forces, atom_energy, n_rep);
+  });
+}
+
+nq_status nq_energy_forces_domain(nq_ctx* ctx, const nq_model* model, const double* pos,
+                                  const int32_t* species, int64_t n_local, int64_t n_total, const double cell[3],
+                                  double* energy, double* forces, double* atom_energy) {
+  return guarded(ctx, [&] {
+    check_common(ctx, model, pos, species, n_total, cell);
+    NQ_REQUIRE(n_local >= 1 && n_local <= n_total, NQ_ERR_ARG, "need 1 <= n_local <= n_total");
+    NQ_REQUIRE(energy && forces, NQ_ERR_ARG, "null output");
+    NQ_HIP(hipSetDevice(ctx->device));
+    ensure_list(ctx, model, pos, n_total, cell);
+    evaluate_async(ctx, model, pos, species, n_total, energy, forces, atom_energy, 1, n_local);
   });
 }
 

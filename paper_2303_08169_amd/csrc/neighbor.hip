@@ -195,14 +195,16 @@ __global__ void k_displacement(const double* __restrict__ pos, const double* __r
 }
 
 // ---- per-evaluation edge list
+// Atoms a >= n_centres (ghosts of a spatial domain) are not centres: their
+// edge rows are empty.
 __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_edge_count(
-    const double* __restrict__ pos, int64_t n, double Lx, double Ly, double Lz, double rc2,
+    const double* __restrict__ pos, int64_t n, int64_t n_centres, double Lx, double Ly, double Lz, double rc2,
     const int* __restrict__ nbr, const int* __restrict__ nbr_cnt, int k_max, int* ecnt) {
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t a = (int64_t)blockIdx.x * kRowsPerBlock + w;
   if (a >= n) return;
   const double ax = pos[3 * a], ay = pos[3 * a + 1], az = pos[3 * a + 2];
-  const int cnt = nbr_cnt[a];
+  const int cnt = a < n_centres ? nbr_cnt[a] : 0;
   int total = 0;
   for (int base = 0; base < cnt; base += kWave) {
     int k = base + lane;
@@ -219,14 +221,14 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_edge_count(
 }
 
 __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_edge_fill(
-    const double* __restrict__ pos, int64_t n, double Lx, double Ly, double Lz, double rc2,
+    const double* __restrict__ pos, int64_t n, int64_t n_centres, double Lx, double Ly, double Lz, double rc2,
     const int* __restrict__ nbr, const int* __restrict__ nbr_cnt, int k_max,
     const int* __restrict__ eoff, int64_t cap, int* ei, int* ej, float4* rij, int* flags) {
   const int w = threadIdx.x / kWave, lane = threadIdx.x % kWave;
   const int64_t a = (int64_t)blockIdx.x * kRowsPerBlock + w;
   if (a >= n) return;
   const double ax = pos[3 * a], ay = pos[3 * a + 1], az = pos[3 * a + 2];
-  const int cnt = nbr_cnt[a];
+  const int cnt = a < n_centres ? nbr_cnt[a] : 0;
   int64_t out = eoff[a];
   for (int base = 0; base < cnt; base += kWave) {
     int k = base + lane;
@@ -253,6 +255,8 @@ __global__ __launch_bounds__(kWave * kRowsPerBlock) void k_edge_fill(
   }
 }
 
+// Slot of the reverse edge (j, i) of every edge (i, j), or INT_MAX when there
+// is none (j is a ghost, which is no centre).
 __global__ void k_edge_rev(const int* __restrict__ nedge, const int* __restrict__ ei,
                            const int* __restrict__ ej, const int* __restrict__ eoff, int* rev) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -264,7 +268,7 @@ __global__ void k_edge_rev(const int* __restrict__ nedge, const int* __restrict_
     int mid = (lo + hi) >> 1;
     if (ej[mid] < i) lo = mid + 1; else hi = mid;
   }
-  rev[e] = lo;
+  rev[e] = (lo < min(eoff[j + 1], ne) && ej[lo] == i) ? lo : 0x7fffffff;
 }
 
 // nedge = min(total, cap); an overflow is reported through flags[4].
@@ -370,20 +374,21 @@ void nbr_displacement_check_async(nq_ctx* ctx, const double* pos, double half) {
   NQ_HIP(hipGetLastError());
 }
 
-void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut) {
+void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut, int64_t n_centres) {
   NbrList& nl = ctx->nl;
   Workspace& ws = ctx->ws;
   const int64_t n = nl.n;
+  if (n_centres < 0) n_centres = n;
   hipStream_t s = ctx->stream;
   const double rc2 = r_cut * r_cut;
   const int blocks = (int)cdiv(n, kRowsPerBlock);
-  k_edge_count<<<blocks, kWave * kRowsPerBlock, 0, s>>>(pos, n, nl.box[0], nl.box[1], nl.box[2], rc2,
+  k_edge_count<<<blocks, kWave * kRowsPerBlock, 0, s>>>(pos, n, n_centres, nl.box[0], nl.box[1], nl.box[2], rc2,
                                                          nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max,
                                                          ws.ecnt.as<int>());
   k_scan_block<<<1, 1024, 0, s>>>(ws.ecnt.as<int>(), ws.eoff.as<int>(), nullptr, n, nullptr, 0);
   // the total edge count lives in eoff[n]
   k_set_edge_count<<<1, 1, 0, s>>>(ws.eoff.as<int>() + n, ws.nedge.as<int>(), ws.cap_all, nl.flags.as<int>());
-  k_edge_fill<<<blocks, kWave * kRowsPerBlock, 0, s>>>(pos, n, nl.box[0], nl.box[1], nl.box[2], rc2,
+  k_edge_fill<<<blocks, kWave * kRowsPerBlock, 0, s>>>(pos, n, n_centres, nl.box[0], nl.box[1], nl.box[2], rc2,
                                                         nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max,
                                                         ws.eoff.as<int>(), ws.cap_all, ws.ei.as<int>(),
                                                         ws.ej.as<int>(), ws.rij.as<float4>(),

@@ -210,7 +210,8 @@ namespace nq {
 void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, double skin, int64_t n_rep = 1);
 void nbr_build_async(nq_ctx* ctx, const double* pos, bool predicated);
 void nbr_displacement_check_async(nq_ctx* ctx, const double* pos, double half_margin);
-void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut);
+// Edges of centres a < n_centres (all atoms when n_centres < 0).
+void edges_build_async(nq_ctx* ctx, const double* pos, double r_cut, int64_t n_centres = -1);
 
 // ---- model (model.cpp)
 Dims make_dims(const nq_model_desc& d);
@@ -223,7 +224,10 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
 void chunk_view_async(nq_ctx* ctx, int chunk);
 void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy);
 void backward_async(nq_ctx* ctx, const nq_model* m);
-void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep = 1);
+// Energies (one per replica) and forces of all atoms; atoms a >= n_centres
+// (ghosts) also gather the edges that point at them through the neighbour list.
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep = 1,
+                  int64_t n_centres = -1);
 
 int gemm_variant_count(int prec, int NP);
 

@@ -943,18 +943,44 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
 }
 
 // F_a = sum over edges (a, j): g(a,j) - g(j,a)   (F_i += g_ij, F_j -= g_ij)
-__global__ void k_forces(int64_t n, const int* __restrict__ nedge_p, const int* __restrict__ eoff,
-                         const int* __restrict__ rev, const float4* __restrict__ gr, double* __restrict__ F) {
+// F_a = sum over a's edges (a, j) of g(a, j) - g(j, a). A centre's incoming
+// edges are the reverses of its own; an atom a >= n_centres (a ghost of a
+// spatial domain: no edges of its own) gathers the edges (j, a) of its centre
+// neighbours j through its neighbour-list row (binary search in j's edge row).
+__global__ void k_forces(int64_t n, int64_t n_centres, const int* __restrict__ nedge_p,
+                         const int* __restrict__ eoff, const int* __restrict__ ej, const int* __restrict__ rev,
+                         const int* __restrict__ nbr, const int* __restrict__ nbr_cnt, int k_max,
+                         const float4* __restrict__ gr, double* __restrict__ F) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
   const int ne = *nedge_p;
   double fx = 0, fy = 0, fz = 0;
-  for (int e = min(eoff[a], ne); e < min(eoff[a + 1], ne); ++e) {
-    const int r = rev[e];
-    const float4 g = gr[e], h = (r < ne) ? gr[r] : make_float4(0.f, 0.f, 0.f, 0.f);
-    fx += (double)g.x - (double)h.x;
-    fy += (double)g.y - (double)h.y;
-    fz += (double)g.z - (double)h.z;
+  if (a < n_centres) {
+    for (int e = min(eoff[a], ne); e < min(eoff[a + 1], ne); ++e) {
+      const int r = rev[e];
+      const float4 g = gr[e], h = (r < ne) ? gr[r] : make_float4(0.f, 0.f, 0.f, 0.f);
+      fx += (double)g.x - (double)h.x;
+      fy += (double)g.y - (double)h.y;
+      fz += (double)g.z - (double)h.z;
+    }
+  } else {
+    const int cnt = nbr_cnt[a];
+    for (int s = 0; s < cnt; ++s) {
+      const int j = nbr[a * (int64_t)k_max + s];
+      if (j >= n_centres) continue;
+      int lo = min(eoff[j], ne), hi = min(eoff[j + 1], ne);
+      const int end = hi;
+      while (lo < hi) {
+        const int mid = (lo + hi) >> 1;
+        if (ej[mid] < a) lo = mid + 1; else hi = mid;
+      }
+      if (lo < end && ej[lo] == a) {
+        const float4 h = gr[lo];
+        fx -= (double)h.x;
+        fy -= (double)h.y;
+        fz -= (double)h.z;
+      }
+    }
   }
   F[3 * a] = fx;
   F[3 * a + 1] = fy;
@@ -1601,7 +1627,8 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
 }
 
 // Whole-system totals after every chunk: compensated energy and force gather.
-void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep) {
+void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep,
+                  int64_t n_centres) {
   Workspace& ws = ctx->ws;
   hipStream_t s = ctx->stream;
   const int64_t n = ws.n_atoms;
@@ -1609,8 +1636,10 @@ void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces
   k_total_energy<<<(unsigned)n_rep, 1024, 0, s>>>(n / n_rep, ws.atomE, energy);
   span_end(ctx, sp);
   sp = span_begin(ctx, "forces");
-  k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, ws.nedge.as<int>(), ws.eoff.as<int>(), ws.rev.as<int>(), ws.gr,
-                                            forces);
+  const NbrList& nl = ctx->nl;
+  k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, n_centres < 0 ? n : n_centres, ws.nedge.as<int>(),
+                                            ws.eoff.as<int>(), ws.ej.as<int>(), ws.rev.as<int>(),
+                                            nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max, ws.gr, forces);
   span_end(ctx, sp);
   NQ_HIP(hipGetLastError());
 }

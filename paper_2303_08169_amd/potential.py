@@ -115,6 +115,20 @@ class Potential:
                                                    _cell(box), _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
         return (E, F, Ei) if atom_energy else (E, F)
 
+    def energy_forces_domain(self, pos, species, n_local, box, atom_energy=False):
+        """One spatial domain: pos [n, 3] with the n_local owned atoms first and
+        ghosts after -> (E of the owned centres [1], F of all n atoms [n, 3][,
+        E_i [n]]); box must leave r_c + skin of empty space around the atoms."""
+        self._check_inputs(pos, species)
+        n = pos.shape[0]
+        F = torch.empty((n, 3), dtype=torch.float64, device=self.device)
+        E = torch.empty(1, dtype=torch.float64, device=self.device)
+        Ei = torch.empty(n, dtype=torch.float64, device=self.device) if atom_energy else None
+        self._sync_stream()
+        B.check(self.lib.nq_energy_forces_domain(self._ctx, self._model, _ptr(pos), _ptr(species), int(n_local), n,
+                                                 _cell(box), _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
+        return (E, F, Ei) if atom_energy else (E, F)
+
     def ring_polymer(self, pos, inv_mass, box, temperature, forces, energy=None):
         """Adds the ring-polymer spring forces of the beads pos [R, n, 3] to
         forces [R, n, 3] and returns the spring energy [1] (eV)."""

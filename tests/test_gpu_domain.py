@@ -1,0 +1,74 @@
+"""One GPU's share of a spatial decomposition: owned atoms plus ghost copies.
+
+The periodic 1,024-atom system is cut into two slabs; each slab is evaluated
+as owned atoms + ghost images within the cutoff in an open frame. The domain
+energies must add up to the periodic energy and the domain forces, with every
+ghost's force added back to the atom it copies (the reverse exchange), must
+reproduce the periodic forces; owned atoms' E_i must match and ghosts' be 0."""
+import numpy as np
+import pytest
+import torch
+
+from tests.gpu_common import rel_rms, system
+
+pytestmark = pytest.mark.gpu
+
+
+def _domain(pos, L, x0, x1, rc, margin):
+    """Owned atoms (x in [x0, x1)) then ghosts, as coordinates in an open frame."""
+    own = np.where((pos[:, 0] >= x0) & (pos[:, 0] < x1))[0]
+    ghosts, src = [], []
+    for sx in (-1, 0, 1):
+        for sy in (-1, 0, 1):
+            for sz in (-1, 0, 1):
+                q = pos + L * np.array([sx, sy, sz])
+                keep = ((q[:, 0] >= x0 - rc) & (q[:, 0] < x1 + rc) & (q[:, 1] >= -rc) & (q[:, 1] < L + rc) &
+                        (q[:, 2] >= -rc) & (q[:, 2] < L + rc))
+                if (sx, sy, sz) == (0, 0, 0):
+                    keep[own] = False
+                idx = np.where(keep)[0]
+                ghosts.append(q[idx])
+                src.append(idx)
+    g, gi = np.concatenate(ghosts), np.concatenate(src)
+    shift = np.array([rc + margin - x0, rc + margin, rc + margin])
+    frame = np.array([x1 - x0 + 2 * (rc + margin), L + 2 * (rc + margin), L + 2 * (rc + margin)])
+    return np.concatenate([pos[own], g]) + shift, np.concatenate([own, gi]), len(own), frame
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_two_slab_decomposition(prec):
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_1024_l2")
+    rc = cf.model.r_cut
+    pot = Potential(cf.model, w, prec)
+    P = torch.tensor(pos, device="cuda")
+    Z = torch.tensor(z, dtype=torch.int32, device="cuda")
+    E0, F0, A0 = pot.energy_forces(P, Z, L, atom_energy=True)
+    E0, F0, A0 = E0.item(), F0.cpu().numpy(), A0.cpu().numpy()
+    E, F = 0.0, np.zeros_like(F0)
+    for x0, x1 in ((0.0, L / 2), (L / 2, L)):
+        q, orig, n_own, frame = _domain(pos, L, x0, x1, rc, margin=8.0)
+        Ed, Fd, Ad = pot.energy_forces_domain(torch.tensor(q, device="cuda"),
+                                              torch.tensor(z[orig], dtype=torch.int32, device="cuda"),
+                                              n_own, frame, atom_energy=True)
+        Ad = Ad.cpu().numpy()
+        assert np.all(Ad[n_own:] == 0.0)
+        np.testing.assert_allclose(Ad[:n_own], A0[orig[:n_own]], rtol=1e-5, atol=1e-6 * np.abs(A0).max())
+        E += Ed.item()
+        np.add.at(F, orig, Fd.cpu().numpy())
+    assert abs(E - E0) <= 1e-6 * abs(E0)
+    assert rel_rms(F, F0) <= 1e-5
+    pot.close()
+
+
+def test_domain_arguments_rejected():
+    from paper_2303_08169_amd import binding as B
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_64_l1")
+    pot = Potential(cf.model, w, "fp32")
+    P = torch.tensor(pos, device="cuda")
+    Z = torch.tensor(z, dtype=torch.int32, device="cuda")
+    for n_local in (0, len(pos) + 1):
+        with pytest.raises(B.NQError):
+            pot.energy_forces_domain(P, Z, n_local, L)
+    pot.close()
