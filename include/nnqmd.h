@@ -168,6 +168,29 @@ nq_status nq_step(nq_ctx* ctx, const nq_model* model, double* pos, double* vel,
                   const double* inv_mass, const int32_t* species, int64_t n, const double cell[3],
                   double dt_fs, int32_t n_steps, double* forces, double* epot, double* ekin);
 
+/* n_steps velocity-Verlet steps with one Nose-Hoover thermostat (the NVT
+ * thermalisation of the robustness protocol, Sec. 3.2): each step is a
+ * thermostat half step, the nq_step velocity-Verlet step, a thermostat half
+ * step; a half step of length h = dt/2 with G(K) = (2K - N_f k_B T)/Q,
+ * Q = N_f k_B T tau^2, N_f = 3n - 3:
+ *   xi += G(K) h/2; v *= exp(-xi h); eta += xi h; xi += G(K) h/2.
+ * thermostat[2] (device, FP64, in/out): xi (1/fs) and eta, zero to start.
+ * temperature in K, tau_fs > 0. epot/ekin as in nq_step (ekin after the last
+ * half step); ethermo[n_steps] (device, FP64, or NULL) receives
+ * Q xi^2/2 + N_f k_B T eta, so epot + ekin + ethermo is conserved. Other
+ * arguments, graph replay and rebuilds as in nq_step. */
+nq_status nq_step_nvt(nq_ctx* ctx, const nq_model* model, double* pos, double* vel,
+                      const double* inv_mass, const int32_t* species, int64_t n, const double cell[3],
+                      double dt_fs, int32_t n_steps, double temperature, double tau_fs, double* thermostat,
+                      double* forces, double* epot, double* ekin, double* ethermo);
+
+/* Outlier count of a force array (the robustness measure of Sec. 3.2, force
+ * values beyond 5 sigma): over the 3n components of forces[n*3] (device,
+ * FP64), their mean mu and standard deviation sigma; count[1] (device, int32)
+ * receives the number of components with |F_k - mu| > nsigma sigma.
+ * Asynchronous; nsigma > 0. */
+nq_status nq_force_outliers(nq_ctx* ctx, const double* forces, int64_t n, double nsigma, int32_t* count);
+
 /* Number of in-cutoff directed edges of the last nq_energy_forces / nq_step
  * evaluation, and of neighbour-list rebuilds so far. Synchronises the stream. */
 nq_status nq_stats(nq_ctx* ctx, int64_t* n_edges, int64_t* n_rebuilds);

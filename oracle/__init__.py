@@ -23,9 +23,9 @@ from .sh import real_sh, real_sh_grad, tp_paths, clebsch_gordan
 from .radial import envelope, bessel
 from .neighbors import edge_list
 from .model import weight_segments, unpack_weights, energy_forces, EdgeTrace
-from .md import velocity_verlet
+from .md import velocity_verlet, nose_hoover
 from .pimd import ring_polymer, omega_p
 
 __all__ = ["real_sh", "real_sh_grad", "tp_paths", "clebsch_gordan", "envelope", "bessel",
            "edge_list", "weight_segments", "unpack_weights", "energy_forces", "EdgeTrace",
-           "velocity_verlet", "ring_polymer", "omega_p"]
+           "velocity_verlet", "nose_hoover", "ring_polymer", "omega_p"]

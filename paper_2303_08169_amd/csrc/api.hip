@@ -315,6 +315,17 @@ nq_status nq_energy_forces_domain(nq_ctx* ctx, const nq_model* model, const doub
   });
 }
 
+nq_status nq_force_outliers(nq_ctx* ctx, const double* forces, int64_t n, double nsigma, int32_t* count) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && forces && count, NQ_ERR_ARG, "null argument");
+    NQ_REQUIRE(n >= 1 && n < ((int64_t)1 << 30), NQ_ERR_ARG, "n out of range");
+    NQ_REQUIRE(std::isfinite(nsigma) && nsigma > 0, NQ_ERR_ARG, "bad nsigma");
+    NQ_HIP(hipSetDevice(ctx->device));
+    force_outliers_async(ctx->stream, forces, n, nsigma, count);
+    NQ_HIP(hipGetLastError());
+  });
+}
+
 nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n, int64_t n_rep,
                           const double cell[3], double temperature, double* forces, double* energy) {
   return guarded(ctx, [&] {
@@ -332,75 +343,129 @@ nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass
   });
 }
 
+namespace {
+
+// Thermostat of an NVT run (null for NVE).
+struct NhParams {
+  double temperature, tau, nfkT, Q;
+  double* state;    // device [2]: xi (1/fs), eta
+  double* ethermo;  // device [n_steps] or null
+};
+
+// n_steps MD steps replayed from one captured HIP graph; see nq_step / nq_step_nvt.
+void md_run(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const double* inv_mass,
+            const int32_t* species, int64_t n, const double cell[3], double dt_fs, int32_t n_steps,
+            double* forces, double* epot, double* ekin, const NhParams* nh) {
+  check_common(ctx, model, pos, species, n, cell);
+  NQ_REQUIRE(vel && inv_mass && forces, NQ_ERR_ARG, "null argument");
+  NQ_REQUIRE(n_steps >= 0 && std::isfinite(dt_fs) && dt_fs > 0, NQ_ERR_ARG, "bad dt or n_steps");
+  if (n_steps == 0) return;
+  NQ_HIP(hipSetDevice(ctx->device));
+  ensure_list(ctx, model, pos, n, cell);
+  if (!ctx->md_stream) {
+    NQ_HIP(hipStreamCreateWithFlags(&ctx->md_stream, hipStreamNonBlocking));
+    NQ_HIP(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
+    NQ_HIP(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
+  }
+  ctx->md_scratch.ensure(128);
+  double* ek_now = ctx->md_scratch.as<double>();
+  int* counter = reinterpret_cast<int*>(ctx->md_scratch.as<double>() + 2);
+  double* nh_K = ctx->md_scratch.as<double>() + 4;      // kinetic energy tracked by the thermostat
+  double* nh_scale = ctx->md_scratch.as<double>() + 5;  // velocity scale of the last half step
+  std::vector<const void*> key = {model,  pos,  vel,  inv_mass, species, forces,
+                                  epot,   ekin, (const void*)(intptr_t)n,
+                                  (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
+                                  (const void*)(intptr_t)ctx->ws.chunks.size(),
+                                  ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p,
+                                  ctx->md_scratch.p};
+  auto push_double = [&](double v) {
+    int64_t b;
+    std::memcpy(&b, &v, sizeof(double));
+    key.push_back((const void*)(intptr_t)b);
+  };
+  push_double(dt_fs);
+  for (int k = 0; k < 3; ++k) push_double(cell[k]);
+  key.push_back(nh ? nh->state : nullptr);
+  key.push_back(nh ? nh->ethermo : nullptr);
+  push_double(nh ? nh->nfkT : 0.0);
+  push_double(nh ? nh->Q : 0.0);
+  hipStream_t user = ctx->stream;
+  if (!ctx->graph_exec || key != ctx->graph_key) {
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+    }
+    ctx->stream = ctx->md_stream;
+    hipGraph_t graph = nullptr;
+    try {
+      NQ_HIP(hipStreamBeginCapture(ctx->md_stream, hipStreamCaptureModeThreadLocal));
+      const double h = 0.5 * dt_fs;
+      if (nh) md_nh_half_async(ctx->md_stream, vel, n, nh->state, nh->state + 1, nh_K, nh_scale, nh->nfkT, nh->Q, h);
+      md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
+      md_drift_async(ctx->md_stream, pos, vel, n, dt_fs, cell);
+      evaluate_async(ctx, model, pos, species, n, ctx->ws.esum, forces, nullptr);
+      md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
+      if (nh) {
+        md_ekin_async(ctx->md_stream, vel, inv_mass, n, nh_K);
+        md_nh_half_async(ctx->md_stream, vel, n, nh->state, nh->state + 1, nh_K, nh_scale, nh->nfkT, nh->Q, h);
+        md_nh_record_async(ctx->md_stream, nh->state, nh->state + 1, counter, nh->ethermo, n_steps, nh->nfkT,
+                           nh->Q);
+        md_record_async(ctx->md_stream, ctx->ws.esum, nh_K, counter, epot, ekin, n_steps);
+      } else {
+        md_ekin_async(ctx->md_stream, vel, inv_mass, n, ek_now);
+        md_record_async(ctx->md_stream, ctx->ws.esum, ek_now, counter, epot, ekin, n_steps);
+      }
+      NQ_HIP(hipStreamEndCapture(ctx->md_stream, &graph));
+      NQ_HIP(hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0));
+      (void)hipGraphDestroy(graph);
+    } catch (...) {
+      hipGraph_t dummy = nullptr;
+      (void)hipStreamEndCapture(ctx->md_stream, &dummy);
+      if (dummy) (void)hipGraphDestroy(dummy);
+      if (graph) (void)hipGraphDestroy(graph);
+      ctx->stream = user;
+      throw;
+    }
+    ctx->stream = user;
+    ctx->graph_key = key;
+  }
+  NQ_HIP(hipEventRecord(ctx->ev[0], user));
+  NQ_HIP(hipStreamWaitEvent(ctx->md_stream, ctx->ev[0], 0));
+  md_set_int_async(ctx->md_stream, counter, 0);
+  if (nh) md_ekin_async(ctx->md_stream, vel, inv_mass, n, nh_K);  // K of the starting velocities
+  for (int s = 0; s < n_steps; ++s) NQ_HIP(hipGraphLaunch(ctx->graph_exec, ctx->md_stream));
+  NQ_HIP(hipEventRecord(ctx->ev[1], ctx->md_stream));
+  NQ_HIP(hipStreamWaitEvent(user, ctx->ev[1], 0));
+  NQ_HIP(hipStreamSynchronize(ctx->md_stream));
+  check_flags(ctx);
+}
+
+}  // namespace
+
 nq_status nq_step(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const double* inv_mass,
                   const int32_t* species, int64_t n, const double cell[3], double dt_fs, int32_t n_steps,
                   double* forces, double* epot, double* ekin) {
   return guarded(ctx, [&] {
-    check_common(ctx, model, pos, species, n, cell);
-    NQ_REQUIRE(vel && inv_mass && forces, NQ_ERR_ARG, "null argument");
-    NQ_REQUIRE(n_steps >= 0 && std::isfinite(dt_fs) && dt_fs > 0, NQ_ERR_ARG, "bad dt or n_steps");
-    if (n_steps == 0) return;
-    NQ_HIP(hipSetDevice(ctx->device));
-    ensure_list(ctx, model, pos, n, cell);
-    if (!ctx->md_stream) {
-      NQ_HIP(hipStreamCreateWithFlags(&ctx->md_stream, hipStreamNonBlocking));
-      NQ_HIP(hipEventCreateWithFlags(&ctx->ev[0], hipEventDisableTiming));
-      NQ_HIP(hipEventCreateWithFlags(&ctx->ev[1], hipEventDisableTiming));
-    }
-    ctx->md_scratch.ensure(64);
-    double* ek_now = ctx->md_scratch.as<double>();
-    int* counter = reinterpret_cast<int*>(ctx->md_scratch.as<double>() + 2);
-    std::vector<const void*> key = {model,  pos,  vel,  inv_mass, species, forces,
-                                    epot,   ekin, (const void*)(intptr_t)n,
-                                    (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
-                                    (const void*)(intptr_t)ctx->ws.chunks.size(),
-                                    ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p};
-    double dtkey;
-    std::memcpy(&dtkey, &dt_fs, sizeof(double));
-    key.push_back((const void*)(intptr_t)(*(int64_t*)&dtkey));
-    for (int k = 0; k < 3; ++k) {
-      int64_t b;
-      std::memcpy(&b, &cell[k], 8);
-      key.push_back((const void*)(intptr_t)b);
-    }
-    hipStream_t user = ctx->stream;
-    if (!ctx->graph_exec || key != ctx->graph_key) {
-      if (ctx->graph_exec) {
-        (void)hipGraphExecDestroy(ctx->graph_exec);
-        ctx->graph_exec = nullptr;
-      }
-      ctx->stream = ctx->md_stream;
-      hipGraph_t graph = nullptr;
-      try {
-        NQ_HIP(hipStreamBeginCapture(ctx->md_stream, hipStreamCaptureModeThreadLocal));
-        md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
-        md_drift_async(ctx->md_stream, pos, vel, n, dt_fs, cell);
-        evaluate_async(ctx, model, pos, species, n, ctx->ws.esum, forces, nullptr);
-        md_half_kick_async(ctx->md_stream, vel, forces, inv_mass, n, 0.5 * dt_fs);
-        md_ekin_async(ctx->md_stream, vel, inv_mass, n, ek_now);
-        md_record_async(ctx->md_stream, ctx->ws.esum, ek_now, counter, epot, ekin, n_steps);
-        NQ_HIP(hipStreamEndCapture(ctx->md_stream, &graph));
-        NQ_HIP(hipGraphInstantiate(&ctx->graph_exec, graph, nullptr, nullptr, 0));
-        (void)hipGraphDestroy(graph);
-      } catch (...) {
-        hipGraph_t dummy = nullptr;
-        (void)hipStreamEndCapture(ctx->md_stream, &dummy);
-        if (dummy) (void)hipGraphDestroy(dummy);
-        if (graph) (void)hipGraphDestroy(graph);
-        ctx->stream = user;
-        throw;
-      }
-      ctx->stream = user;
-      ctx->graph_key = key;
-    }
-    NQ_HIP(hipEventRecord(ctx->ev[0], user));
-    NQ_HIP(hipStreamWaitEvent(ctx->md_stream, ctx->ev[0], 0));
-    md_set_int_async(ctx->md_stream, counter, 0);
-    for (int s = 0; s < n_steps; ++s) NQ_HIP(hipGraphLaunch(ctx->graph_exec, ctx->md_stream));
-    NQ_HIP(hipEventRecord(ctx->ev[1], ctx->md_stream));
-    NQ_HIP(hipStreamWaitEvent(user, ctx->ev[1], 0));
-    NQ_HIP(hipStreamSynchronize(ctx->md_stream));
-    check_flags(ctx);
+    md_run(ctx, model, pos, vel, inv_mass, species, n, cell, dt_fs, n_steps, forces, epot, ekin, nullptr);
+  });
+}
+
+nq_status nq_step_nvt(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const double* inv_mass,
+                      const int32_t* species, int64_t n, const double cell[3], double dt_fs, int32_t n_steps,
+                      double temperature, double tau_fs, double* thermostat, double* forces, double* epot,
+                      double* ekin, double* ethermo) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(thermostat, NQ_ERR_ARG, "null thermostat state");
+    NQ_REQUIRE(std::isfinite(temperature) && temperature > 0 && std::isfinite(tau_fs) && tau_fs > 0, NQ_ERR_ARG,
+               "bad temperature or tau");
+    NhParams nh;
+    nh.temperature = temperature;
+    nh.tau = tau_fs;
+    nh.nfkT = (double)(3 * n - 3) * 8.617333262e-5 * temperature;  // k_B in eV/K
+    nh.Q = nh.nfkT * tau_fs * tau_fs;
+    nh.state = thermostat;
+    nh.ethermo = ethermo;
+    md_run(ctx, model, pos, vel, inv_mass, species, n, cell, dt_fs, n_steps, forces, epot, ekin, &nh);
   });
 }
 

@@ -69,6 +69,72 @@ __global__ void k_record(const double* __restrict__ epot_now, const double* __re
 
 __global__ void k_set_int(int* p, int v) { *p = v; }
 
+// One Nose-Hoover thermostat half step of length h (constant-temperature
+// runs of the robustness protocol, paper Sec. 3.2), single thread. With
+// G(K) = (2K - N_f k_B T) / Q:
+//   xi += G(K) h/2;  scale = exp(-xi h);  K *= scale^2;  eta += xi h;  xi += G(K) h/2,
+// and the velocities are then multiplied by scale (k_scale_vel).
+__global__ void k_nh_half(double* __restrict__ xi, double* __restrict__ eta, double* __restrict__ K,
+                          double* __restrict__ scale, double nfkT, double Q, double h) {
+  double x = xi[0], k = K[0];
+  x += (2.0 * k - nfkT) / Q * 0.5 * h;
+  const double sc = exp(-x * h);
+  k *= sc * sc;
+  eta[0] += x * h;
+  x += (2.0 * k - nfkT) / Q * 0.5 * h;
+  xi[0] = x;
+  K[0] = k;
+  scale[0] = sc;
+}
+
+__global__ void k_scale_vel(double* __restrict__ vel, int64_t n, const double* __restrict__ scale) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (k < 3 * n) vel[k] *= scale[0];
+}
+
+// Thermostat energy Q xi^2 / 2 + N_f k_B T eta of the step being recorded.
+__global__ void k_nh_record(const double* __restrict__ xi, const double* __restrict__ eta, const int* counter,
+                            double* ethermo, int n_steps, double nfkT, double Q) {
+  const int s = *counter;
+  if (s < n_steps && ethermo) ethermo[s] = 0.5 * Q * xi[0] * xi[0] + nfkT * eta[0];
+}
+
+// Force outliers (the robustness measure of paper Sec. 3.2: force values
+// beyond 5 sigma): over the 3n components of F, the mean mu and standard
+// deviation sigma, then count[0] = #{k : |F_k - mu| > nsigma sigma}. One block.
+__global__ __launch_bounds__(1024) void k_force_outliers(const double* __restrict__ F, int64_t m, double nsigma,
+                                                         int* __restrict__ count) {
+  __shared__ double s1[1024], s2[1024];
+  __shared__ int sc[1024];
+  double a = 0.0, b = 0.0;
+  for (int64_t k = threadIdx.x; k < m; k += blockDim.x) {
+    a += F[k];
+    b += F[k] * F[k];
+  }
+  s1[threadIdx.x] = a;
+  s2[threadIdx.x] = b;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) {
+      s1[threadIdx.x] += s1[threadIdx.x + o];
+      s2[threadIdx.x] += s2[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  const double mu = s1[0] / (double)m;
+  const double var = s2[0] / (double)m - mu * mu;
+  const double lim = nsigma * sqrt(var > 0.0 ? var : 0.0);
+  int c = 0;
+  for (int64_t k = threadIdx.x; k < m; k += blockDim.x) c += fabs(F[k] - mu) > lim;
+  sc[threadIdx.x] = c;
+  __syncthreads();
+  for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+    if ((int)threadIdx.x < o) sc[threadIdx.x] += sc[threadIdx.x + o];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) count[0] = sc[0];
+}
+
 __device__ inline double mic(double d, double L) { return d - L * rint(d / L); }
 
 // Harmonic coupling of the R beads (replicas) of every atom into a ring
@@ -142,6 +208,21 @@ void md_record_async(hipStream_t s, const double* epot_now, const double* ekin_n
 }
 
 void md_set_int_async(hipStream_t s, int* p, int v) { k_set_int<<<1, 1, 0, s>>>(p, v); }
+
+void md_nh_half_async(hipStream_t s, double* vel, int64_t n, double* xi, double* eta, double* K, double* scale,
+                      double nfkT, double Q, double h) {
+  k_nh_half<<<1, 1, 0, s>>>(xi, eta, K, scale, nfkT, Q, h);
+  k_scale_vel<<<(unsigned)cdiv(3 * n, 256), 256, 0, s>>>(vel, n, scale);
+}
+
+void md_nh_record_async(hipStream_t s, const double* xi, const double* eta, const int* counter, double* ethermo,
+                        int n_steps, double nfkT, double Q) {
+  k_nh_record<<<1, 1, 0, s>>>(xi, eta, counter, ethermo, n_steps, nfkT, Q);
+}
+
+void force_outliers_async(hipStream_t s, const double* forces, int64_t n, double nsigma, int* count) {
+  k_force_outliers<<<1, 1024, 0, s>>>(forces, 3 * n, nsigma, count);
+}
 
 void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass, int64_t n, int64_t R,
                         double omega_p, const double box[3], double* forces, double* e_bond, double* energy) {

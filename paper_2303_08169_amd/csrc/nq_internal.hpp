@@ -236,6 +236,14 @@ void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const 
                         int64_t n, double half_dt);
 void md_drift_async(hipStream_t s, double* pos, const double* vel, int64_t n, double dt,
                     const double box[3]);
+// Nose-Hoover thermostat half step of length h on vel (xi, eta, K, scale: one
+// device double each), and the record of its energy into ethermo[*counter].
+void md_nh_half_async(hipStream_t s, double* vel, int64_t n, double* xi, double* eta, double* K, double* scale,
+                      double nfkT, double Q, double h);
+void md_nh_record_async(hipStream_t s, const double* xi, const double* eta, const int* counter, double* ethermo,
+                        int n_steps, double nfkT, double Q);
+// count[0] = force components of F[n*3] farther than nsigma standard deviations from their mean.
+void force_outliers_async(hipStream_t s, const double* forces, int64_t n, double nsigma, int* count);
 // Ring-polymer springs of R beads x n atoms: forces += spring forces (eV/A),
 // energy[0] = spring energy (eV); e_bond: n R doubles of scratch.
 void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass, int64_t n, int64_t R,

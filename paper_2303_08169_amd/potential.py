@@ -151,6 +151,25 @@ class Potential:
                                  pos.shape[0], _cell(box), float(dt_fs), int(n_steps), _ptr(forces),
                                  _ptr(epot), _ptr(ekin)), self._ctx)
 
+    def step_nvt(self, pos, vel, inv_mass, species, box, dt_fs, n_steps, temperature, tau_fs, thermostat, forces,
+                 epot=None, ekin=None, ethermo=None):
+        """n_steps Nose-Hoover NVT steps in place; thermostat: device float64 [2]
+        (xi, eta), zero to start; forces must hold F(pos) on entry."""
+        self._check_inputs(pos, species)
+        self._sync_stream()
+        B.check(self.lib.nq_step_nvt(self._ctx, self._model, _ptr(pos), _ptr(vel), _ptr(inv_mass), _ptr(species),
+                                     pos.shape[0], _cell(box), float(dt_fs), int(n_steps), float(temperature),
+                                     float(tau_fs), _ptr(thermostat), _ptr(forces), _ptr(epot), _ptr(ekin),
+                                     _ptr(ethermo)), self._ctx)
+
+    def force_outliers(self, forces, nsigma=5.0):
+        """Number of force components beyond nsigma standard deviations (device int32 [1])."""
+        count = torch.zeros(1, dtype=torch.int32, device=self.device)
+        self._sync_stream()
+        B.check(self.lib.nq_force_outliers(self._ctx, _ptr(forces), forces.shape[0], float(nsigma), _ptr(count)),
+                self._ctx)
+        return count
+
     def autotune(self, pos, species, box, reps: int = 3):
         """Time every tile-shape candidate of every matrix-core product on this
         system and keep the fastest; returns the library's JSON report."""

@@ -78,3 +78,72 @@ def test_short_nve_conserves_energy():
     assert np.abs(etot - etot[0]).max() / len(pos) < 1e-5
     assert np.all(np.isfinite(etot))
     pot.close()
+
+
+def _run_nvt(pot, pos, z, L, dt, n, T_target, tau, T0=300.0):
+    P, V, IM, Z, m, v0 = _state(pos, z, T0)
+    E, F = pot.energy_forces(P, Z, L)
+    th = torch.zeros(2, dtype=torch.float64, device="cuda")
+    ep = torch.zeros(n, dtype=torch.float64, device="cuda")
+    ek = torch.zeros(n, dtype=torch.float64, device="cuda")
+    et = torch.zeros(n, dtype=torch.float64, device="cuda")
+    pot.step_nvt(P, V, IM, Z, L, dt, n, T_target, tau, th, F, ep, ek, et)
+    torch.cuda.synchronize()
+    return (P.cpu().numpy(), V.cpu().numpy(), ep.cpu().numpy(), ek.cpu().numpy(), et.cpu().numpy(),
+            th.cpu().numpy())
+
+
+def test_nvt_matches_oracle_nose_hoover():
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_64_l1")
+    pot = Potential(cf.model, w, "fp32")
+    n, dt, T, tau = 20, 0.5, 200.0, 20.0
+    P, V, ep, ek, et, th = _run_nvt(pot, pos, z, L, dt, n, T, tau)
+    v0 = maxwell_boltzmann(z, 300.0, 200)
+    rp, rv, rep, rek, ret, xi, eta = oracle.nose_hoover(pos, v0, masses(z), L, n, dt,
+                                                        lambda p: oracle.energy_forces(p, z, L, cf.model, w), T, tau)
+    d = P - rp
+    d -= L * np.round(d / L)
+    assert np.abs(d).max() < 1e-7
+    assert np.abs(V - rv).max() < 1e-8
+    np.testing.assert_allclose(ek, rek, rtol=1e-6)
+    np.testing.assert_allclose(et, ret, rtol=1e-6, atol=1e-9)
+    assert abs(th[0] - xi) <= 1e-6 * abs(xi) and abs(th[1] - eta) <= 1e-6 * abs(eta)
+    pot.close()
+
+
+def test_nvt_extended_energy_conserved():
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_64_l1")
+    pot = Potential(cf.model, w, "fp32")
+    P, V, ep, ek, et, th = _run_nvt(pot, pos, z, L, 0.25, 200, 200.0, 10.0)
+    h = ep + ek + et
+    assert np.abs(et).max() > 0.05 * ek.mean()  # the thermostat does work
+    assert np.abs(h - h[0]).max() < 2e-3 * ek.mean()
+    pot.close()
+
+
+def test_force_outliers_by_injection():
+    from paper_2303_08169_amd.potential import Potential
+    cf, pos, z, L, w = system("nh3_64_l1")
+    pot = Potential(cf.model, w, "fp32")
+    P = torch.tensor(pos, device="cuda")
+    Z = torch.tensor(z, dtype=torch.int32, device="cuda")
+    _, F = pot.energy_forces(P, Z, L)
+    torch.cuda.synchronize()
+
+    def count(f, k):
+        x = f.reshape(-1)
+        mu, sd = x.mean(), x.std()
+        return int((np.abs(x - mu) > k * sd).sum())
+
+    f = F.cpu().numpy()
+    assert pot.force_outliers(F, 5.0).item() == count(f, 5.0)
+    assert pot.force_outliers(F, 1.0).item() == count(f, 1.0)
+    G = F.clone()
+    G[3, 1] = 50.0 * float(np.abs(f).max())
+    G[17, 2] = -50.0 * float(np.abs(f).max())
+    g = G.cpu().numpy()
+    got = pot.force_outliers(G, 5.0).item()
+    assert got == count(g, 5.0) and got >= 2
+    pot.close()
