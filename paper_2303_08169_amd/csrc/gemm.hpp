@@ -18,7 +18,9 @@
 
 namespace nq {
 
-__device__ inline float sigmoidf_(float a) { return 1.0f / (1.0f + __expf(-a)); }
+// Logistic function with the hardware reciprocal (1 ulp) instead of an IEEE
+// division, which expands to about ten instructions per call.
+__device__ inline float sigmoidf_(float a) { return __builtin_amdgcn_rcpf(1.0f + __expf(-a)); }
 __device__ inline float siluf(float a) { return a * sigmoidf_(a); }
 __device__ inline float dsiluf(float a) {
   float s = sigmoidf_(a);
@@ -118,59 +120,65 @@ __device__ inline void store_tiles(const Epi& ep, const floatx4 (&acc)[MI][NI], 
   constexpr int JC = NI < 4 ? NI : 4;
 #pragma unroll
   for (int i = 0; i < MI; ++i) {
+    // row base addresses, once per row (64-bit), column offsets 32-bit
+    int64_t rr[4];
+    bool rok[4];
     float rsv[4];
-    if constexpr (kRS) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
-        rsv[q] = ep.rs[(r < nrows ? r : nrows - 1) * ep.rs_ld];
-      }
+    for (int q = 0; q < 4; ++q) {
+      const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
+      rok[q] = r < nrows;
+      rr[q] = rok[q] ? r : nrows - 1;
+      if constexpr (kRS) rsv[q] = ep.rs[rr[q] * ep.rs_ld];
     }
 #pragma unroll
     for (int j0 = 0; j0 < NI; j0 += JC) {
       float in[JC][4];
       if constexpr (kIN) {
 #pragma unroll
-        for (int jj = 0; jj < JC; ++jj)
-#pragma unroll
-          for (int q = 0; q < 4; ++q) {
-            if (j0 + jj >= NI) continue;
-            const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
-            const int64_t rc = r < nrows ? r : nrows - 1;
-            const int c = cbase + (j0 + jj) * 16 + lane % 16;
-            const int cc = c < ep.N0 ? c : 0;
-            if constexpr (MODE == E_RESIDUAL) in[jj][q] = ep.x[rc * ep.ldx + cc];
-            else if constexpr (MODE == E_LATENT_BWD) in[jj][q] = ep.o0[rc * ep.ld0 + (cc < ep.D ? cc : 0)];
-            else in[jj][q] = ep.o0[rc * ep.ld0 + cc];
-          }
-      }
-#pragma unroll
-      for (int jj = 0; jj < JC; ++jj)
-#pragma unroll
         for (int q = 0; q < 4; ++q) {
-          const int j = j0 + jj;
-          if (j >= NI) continue;
-          const int64_t r = rbase + i * 16 + (lane / 16) * 4 + q;
-          const int c = cbase + j * 16 + lane % 16;
-          if (r >= nrows || c >= ep.N0) continue;
-          const float v = acc[i][j][q];
-          if constexpr (MODE == E_STORE) {
-            ep.o0[r * ep.ld0 + c] = v;
-          } else if constexpr (MODE == E_STORE_X0) {
-            ep.o0[r * ep.ld0 + c] = v;
-            ep.o1[r * ep.ld1 + c] = rsv[q] * siluf(v);
-          } else if constexpr (MODE == E_RESIDUAL) {
-            ep.o0[r * ep.ld0 + c] = v;
-            ep.o1[r * ep.ld1 + c] = (in[jj][q] + rsv[q] * siluf(v)) * kInvSqrt2;
-          } else if constexpr (MODE == E_LATENT_BWD) {
-            if (c < ep.D)
-              ep.o0[r * ep.ld0 + c] = in[jj][q] * kInvSqrt2 + v;
-            else
-              ep.o1[r * ep.ld1 + (c - ep.D)] = v;
-          } else {
-            ep.o0[r * ep.ld0 + c] = in[jj][q] + v;
+          const float* src = MODE == E_RESIDUAL ? ep.x + rr[q] * ep.ldx : ep.o0 + rr[q] * ep.ld0;
+#pragma unroll
+          for (int jj = 0; jj < JC; ++jj) {
+            if (j0 + jj >= NI) continue;
+            const int c = cbase + (j0 + jj) * 16 + lane % 16;
+            int cc = c < ep.N0 ? c : 0;
+            if constexpr (MODE == E_LATENT_BWD) cc = cc < ep.D ? cc : 0;
+            in[jj][q] = src[cc];
           }
         }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (!rok[q]) continue;
+        float* o0 = ep.o0 + rr[q] * ep.ld0;
+        float* o1 = (MODE == E_STORE_X0 || MODE == E_RESIDUAL || MODE == E_LATENT_BWD) ? ep.o1 + rr[q] * ep.ld1
+                                                                                          : nullptr;
+#pragma unroll
+        for (int jj = 0; jj < JC; ++jj) {
+          const int j = j0 + jj;
+          if (j >= NI) continue;
+          const int c = cbase + j * 16 + lane % 16;
+          if (c >= ep.N0) continue;
+          const float v = acc[i][j][q];
+          if constexpr (MODE == E_STORE) {
+            o0[c] = v;
+          } else if constexpr (MODE == E_STORE_X0) {
+            o0[c] = v;
+            o1[c] = rsv[q] * siluf(v);
+          } else if constexpr (MODE == E_RESIDUAL) {
+            o0[c] = v;
+            o1[c] = (in[jj][q] + rsv[q] * siluf(v)) * kInvSqrt2;
+          } else if constexpr (MODE == E_LATENT_BWD) {
+            if (c < ep.D)
+              o0[c] = in[jj][q] * kInvSqrt2 + v;
+            else
+              o1[c - ep.D] = v;
+          } else {
+            o0[c] = in[jj][q] + v;
+          }
+        }
+      }
     }
   }
 }
