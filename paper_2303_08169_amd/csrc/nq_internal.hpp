@@ -160,7 +160,7 @@ struct Workspace {
   const float4* v_rij = nullptr;
   float *geo = nullptr, *h0 = nullptr, *we1 = nullptr, *eij = nullptr;
   float *gx = nullptr, *gh[2] = {nullptr, nullptr}, *gs = nullptr, *gv[2] = {nullptr, nullptr};
-  float *ggc = nullptr, *ggam = nullptr, *gew = nullptr, *gY = nullptr, *gu = nullptr;
+  float *ggc = nullptr, *gew = nullptr, *gY = nullptr, *gu = nullptr;
   float4* gr = nullptr;
   double *atomE = nullptr, *esum = nullptr;
   std::vector<float*> a_tb, a_edge, x, gam, s, V, e;

@@ -100,7 +100,16 @@ __global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __rest
     h[S + k] = (k == zj) ? 1.f : 0.f;
   }
   const float pref = 2.f / rc, w = 3.14159265358979323846f / rc;
-  for (int n = 1; n <= nb; ++n) h[2 * S + n - 1] = pref * sinf(n * w * d) * inv * u;
+  // sin(n w d) for n = 1..nb by the angle-addition recurrence from one sincos
+  float s1, c1;
+  sincosf(w * d, &s1, &c1);
+  float sn = s1, cn = c1;
+  for (int n = 1; n <= nb; ++n) {
+    h[2 * S + n - 1] = pref * sn * inv * u;
+    const float t = sn * c1 + cn * s1;
+    cn = cn * c1 - sn * s1;
+    sn = t;
+  }
   for (int k = 2 * S + nb; k < K0p; ++k) h[k] = 0.f;
 }
 
@@ -828,77 +837,71 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
   }
 }
 
-// Per-centre adjoint of the environment sum, part 1:
-// dGamma_i[lm][c] = nu^-1/2 sum_{j: (i,j) edge} ggc[(i,j)][lm][c]
-// (one wavefront per centre, lanes and edge batches as in k_env_fwd).
+// Adjoint of the environment sum Gamma_i = nu^-1/2 sum_k e_k (x) Y_k for one
+// centre per wavefront (lanes: channel c, group g of G = 64 / C):
+//   dGamma_i[lm][c] = nu^-1/2 sum_k ggc[k][lm][c]      (groups split the edges)
+//   de_k[l][c]      = sum_m dGamma_i[lm][c] Y_k[lm]     -> gew[:, gcol + l*C + c]
+//   dY_k[lm]       += sum_c e_k[l][c] dGamma_i[lm][c]   (channel sums spread over lanes)
+// dGamma_i stays in registers between the two passes over the centre's edges.
 template <int NY, int C>
-__global__ __launch_bounds__(256) void k_env_reduce(int64_t n, const int* __restrict__ nedge_p,
-                                                    const int* __restrict__ eoff, const float* __restrict__ ggc,
-                                                    float scale, float* __restrict__ ggam) {
-  constexpr int G = 64 / C, NQ = (NY + G - 1) / G, U = 4;
+__global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __restrict__ nedge_p,
+                                                     const int* __restrict__ eoff, const float* __restrict__ ggc,
+                                                     const float* __restrict__ esrc, int lde,
+                                                     const float* __restrict__ geo, float scale,
+                                                     float* __restrict__ gew, int ldgew, int gcol,
+                                                     float* __restrict__ gY) {
+  constexpr int G = 64 / C, L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= n) return;
   const int lane = threadIdx.x % 64;
   const int c = lane % C, g = lane / C;
-  int lmq[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) lmq[q] = min(g + q * G, NY - 1);
-  float acc[NQ];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q) acc[q] = 0.f;
   const int ne = *nedge_p;
   const int b = min(eoff[i], ne), e1 = min(eoff[i + 1], ne);
-  int e = b;
-  for (; e + U <= e1; e += U) {
-    float v[U][NQ];
+  float dg[NY];
 #pragma unroll
-    for (int u = 0; u < U; ++u)
+  for (int lm = 0; lm < NY; ++lm) dg[lm] = 0.f;
+  int k = b + g;
+  for (; k + G < e1; k += 2 * G) {  // two edges per group in flight
+    float v0[NY], v1[NY];
 #pragma unroll
-      for (int q = 0; q < NQ; ++q) v[u][q] = ggc[((int64_t)(e + u) * NY + lmq[q]) * C + c];
-#pragma unroll
-    for (int u = 0; u < U; ++u)
-#pragma unroll
-      for (int q = 0; q < NQ; ++q) acc[q] += v[u][q];
-  }
-  for (; e < e1; ++e)
-#pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] += ggc[((int64_t)e * NY + lmq[q]) * C + c];
-#pragma unroll
-  for (int q = 0; q < NQ; ++q)
-    if (g + q * G < NY) ggam[(i * NY + g + q * G) * C + c] = acc[q] * scale;
-}
-
-// Part 2, per (edge k, channel c) of centre i:
-// de_k[l][c] = sum_m dGamma_i[lm][c] Y_k[lm]  -> gew[:, gcol + l*C + c]
-// dY_k[lm] += sum_c e_k[l][c] dGamma_i[lm][c]  (reduced over the C lanes of the edge)
-template <int NY>
-__global__ __launch_bounds__(256) void k_env_bwd_edge(const int* __restrict__ nedge_p, const int* __restrict__ ei,
-                                                      const float* __restrict__ ggam, const float* __restrict__ esrc,
-                                                      int lde, const float* __restrict__ geo, int C,
-                                                      float* __restrict__ gew, int ldgew, int gcol,
-                                                      float* __restrict__ gY) {
-  constexpr int L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
-  const int epb = 256 / C;
-  const int el = threadIdx.x / C, c = threadIdx.x % C;
-  const int64_t e = (int64_t)blockIdx.x * epb + el;
-  if (e >= *nedge_p) return;
-  const int64_t i = ei[e];
-  const float* Y = geo + e * kGeo + kGeoY;
-  float ev[L + 1], prod[NY];
-#pragma unroll
-  for (int l = 0; l <= L; ++l) ev[l] = esrc[e * lde + l * C + c];
-#pragma unroll
-  for (int l = 0; l <= L; ++l) {
-    float ge = 0.f;
-#pragma unroll
-    for (int m = 0; m < 2 * l + 1; ++m) {
-      const float gg = ggam[(i * NY + l * l + m) * C + c];
-      ge += gg * Y[l * l + m];
-      prod[l * l + m] = ev[l] * gg;
+    for (int lm = 0; lm < NY; ++lm) {
+      v0[lm] = ggc[((int64_t)k * NY + lm) * C + c];
+      v1[lm] = ggc[((int64_t)(k + G) * NY + lm) * C + c];
     }
-    gew[e * ldgew + gcol + l * C + c] = ge;
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) dg[lm] += v0[lm] + v1[lm];
   }
-  add_group_sums<NY>(prod, C, c, gY + e * 16);
+  if (k < e1) {
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) dg[lm] += ggc[((int64_t)k * NY + lm) * C + c];
+  }
+#pragma unroll
+  for (int o = C; o < 64; o <<= 1)
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) dg[lm] += __shfl_xor(dg[lm], o);
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) dg[lm] *= scale;
+  for (int kk = b + g; kk < e1; kk += G) {
+    const float* Y = geo + (int64_t)kk * kGeo + kGeoY;
+    float ev[L + 1], prod[NY];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) ev[l] = esrc[(int64_t)kk * lde + l * C + c];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) {
+      float ge = 0.f;
+#pragma unroll
+      for (int m = 0; m < 2 * l + 1; ++m) {
+        ge += dg[l * l + m] * Y[l * l + m];
+        prod[l * l + m] = ev[l] * dg[l * l + m];
+      }
+      gew[(int64_t)kk * ldgew + gcol + l * C + c] = ge;
+    }
+    int first = 0, count = 0;
+    spread_sum<NY, C>(prod, c, first, count);
+#pragma unroll
+    for (int q = 0; q < NY; ++q)
+      if (q < count) gY[(int64_t)kk * 16 + first + q] += prod[q];
+  }
 }
 
 __device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, float& gx, float& gy, float& gz) {
@@ -921,15 +924,19 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
   envelope(d / rc, p, u, dudx);
   float gut = gu[e], gd = 0.f;
   const float pref = 2.f / rc, w = 3.14159265358979323846f / rc, inv = 1.f / d;
+  float s1, c1;
+  sincosf(w * d, &s1, &c1);
+  float sn = s1, cs = c1;  // sin, cos of n w d (angle-addition recurrence)
   for (int n = 1; n <= nb; ++n) {
     const float k = n * w;
-    float sn, cs;
-    sincosf(k * d, &sn, &cs);
     const float B = pref * sn * inv;
     const float dB = pref * (k * cs * inv - sn * inv * inv);
     const float gb = gh0[e * ldh0 + boff + n - 1];
     gut += gb * B;
     gd += gb * u * dB;
+    const float t = sn * c1 + cs * s1;
+    cs = cs * c1 - sn * s1;
+    sn = t;
   }
   gd += gut * dudx / rc;
   float gY[9];
@@ -1257,22 +1264,14 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
   const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
   const int lde = t == 1 ? 2 * d.NW : d.NW;
   const float scale = (float)d.inv_sqrt_nu;
-  // per edge: the dE/dGamma contributions; per atom: dE/dGamma written, offsets
-  int sp = span_begin(ctx, "env_reduce" + std::to_string(t), 0, 4.0 * d.NY * d.C, 0, 4.0 * d.NY * d.C + 4.0);
-#define NQ_ENVR(NYV, CV) \
-  k_env_reduce<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, scale, ws.ggam)
-  NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVR);
-#undef NQ_ENVR
-  span_end(ctx, sp);
-  // per edge: centre index, e, Y, dE/de written, dE/dY read-modify-write; per atom: dE/dGamma
-  sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0, 4.0 + 8.0 * d.NW + 4.0 * d.NY + 8.0 * d.NY, 0,
-                  4.0 * d.NY * d.C);
-  if (d.L == 1)
-    k_env_bwd_edge<4><<<grid_for(ws.cap, 256 / d.C), 256, 0, ctx->stream>>>(
-        ws.v_nedge, ws.v_ei, ws.ggam, esrc, lde, ws.geo, d.C, ws.gew, 2 * d.NW, d.NW, ws.gY);
-  else
-    k_env_bwd_edge<9><<<grid_for(ws.cap, 256 / d.C), 256, 0, ctx->stream>>>(
-        ws.v_nedge, ws.v_ei, ws.ggam, esrc, lde, ws.geo, d.C, ws.gew, 2 * d.NW, d.NW, ws.gY);
+  // per edge: the dE/dGamma contributions, e, Y, dE/de written, dE/dY read-modify-write
+  const int sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0,
+                            4.0 * d.NY * d.C + 8.0 * d.NW + 4.0 * d.NY + 8.0 * d.NY, 0, 4.0);
+#define NQ_ENVB(NYV, CV)                                                                                   \
+  k_env_adjoint<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, esrc, lde, \
+                                                                  ws.geo, scale, ws.gew, 2 * d.NW, d.NW, ws.gY)
+  NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVB);
+#undef NQ_ENVB
   NQ_HIP(hipGetLastError());
   span_end(ctx, sp);
 }
@@ -1419,7 +1418,6 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
   ws.gv[0] = fbuf(cap, d.NY * d.C);
   ws.gv[1] = fbuf(cap, d.NY * d.C);
   ws.ggc = fbuf(cap, d.NY * d.C);
-  ws.ggam = fbuf(n_atoms, d.NY * d.C);
   ws.gew = fbuf(cap, 2 * d.NW);
   ws.gY = fbuf(cap, 16);
   ws.gu = fbuf(cap, 1);
