@@ -237,8 +237,15 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
   constexpr int NB = (B16 + 255) / 256;
   static_assert(WM * WN == 4, "4 wavefronts");
   static_assert(RW % 16 == 0 && CW % 16 == 0, "16x16 tiles");
-  __shared__ __attribute__((aligned(16))) AT As[BM * LDA];
-  __shared__ __attribute__((aligned(16))) BT Bs[Tr::BHALVES * NP * LDB];
+  // BF16 weight rows (32 values, four 16-byte chunks) are stored unpadded with
+  // the chunk index XORed by (row / 4) % 4, which keeps both the 16-byte
+  // fragment reads of 16 consecutive rows and the tile stores free of bank
+  // conflicts; FP32 rows keep a padded stride.
+  constexpr bool SWZ = sizeof(BT) == 2;
+  constexpr int LDBS = SWZ ? BK : LDB;
+  constexpr int ABUF = BM * LDA, BBUF = Tr::BHALVES * NP * LDBS;
+  __shared__ __attribute__((aligned(16))) AT As[ABUF];
+  __shared__ __attribute__((aligned(16))) BT Bs[BBUF];
 
   const int64_t nrows = *nrows_p;
   const int64_t r0 = (int64_t)blockIdx.x * BM;
@@ -280,93 +287,105 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
       }                                                                                           \
     }                                                                                             \
   }
+#define NQ_GEMM_SWZ(N, CH) (SWZ ? ((CH) ^ (((N) >> 2) & (CPR - 1))) : (CH))
+  // Writes the fetched tiles of K step ST into LDS.
+#define NQ_GEMM_STORE(ST)                                                                         \
+  {                                                                                               \
+    AT* as_ = As;                                                                                 \
+    BT* bs_ = Bs;                                                                                 \
+    _Pragma("unroll") for (int q = 0; q < NA; ++q) {                                              \
+      const int idx = tid + 256 * q;                                                              \
+      if (idx < A4) {                                                                             \
+        const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;                                 \
+        const float4 v = ld.finish(ra[q], r0 + rr < nrows, (ST) * BK + kk, rd[q]);               \
+        if constexpr (sizeof(AT) == 4) {                                                          \
+          *reinterpret_cast<float4*>(&as_[rr * LDA + kk]) = v;                                    \
+        } else {                                                                                  \
+          typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));                              \
+          bf16x4 b4;                                                                              \
+          b4[0] = (bf16)v.x;                                                                      \
+          b4[1] = (bf16)v.y;                                                                      \
+          b4[2] = (bf16)v.z;                                                                      \
+          b4[3] = (bf16)v.w;                                                                      \
+          *reinterpret_cast<bf16x4*>(&as_[rr * LDA + kk]) = b4;                                   \
+        }                                                                                         \
+      }                                                                                           \
+    }                                                                                             \
+    _Pragma("unroll") for (int q = 0; q < NB; ++q) {                                              \
+      const int idx = tid + 256 * q;                                                              \
+      if (idx < B16) {                                                                            \
+        const int h = idx / (NP * CPR), rem = idx % (NP * CPR);                                   \
+        const int n = rem / CPR, ch = rem % CPR;                                                  \
+        *reinterpret_cast<u32x4*>(&bs_[(h * NP + n) * LDBS + NQ_GEMM_SWZ(n, ch) * EPC]) = rb[q];  \
+      }                                                                                           \
+    }                                                                                             \
+  }
+  // Matrix-core products of the tiles in LDS.
+#define NQ_GEMM_COMPUTE()                                                                           \
+  {                                                                                               \
+    const AT* as_ = As;                                                                           \
+    const BT* bs_ = Bs;                                                                           \
+    if constexpr (KIND == G_BF16) {                                                               \
+      bf16x8 a[MI];                                                                               \
+      _Pragma("unroll") for (int i = 0; i < MI; ++i) a[i] =                                       \
+          *reinterpret_cast<const bf16x8*>(&as_[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8]); \
+      _Pragma("unroll") for (int j = 0; j < NI; ++j) {                                            \
+        const int n = wn * CW + j * 16 + lane % 16;                                               \
+        const bf16x8 b = *reinterpret_cast<const bf16x8*>(&bs_[n * LDBS + NQ_GEMM_SWZ(n, lane / 16) * 8]); \
+        _Pragma("unroll") for (int i = 0; i < MI; ++i) acc[i][j] =                                \
+            __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);                 \
+      }                                                                                           \
+    } else if constexpr (KIND == G_BF16X3) {                                                      \
+      bf16x8 ahi[MI], alo[MI];                                                                    \
+      _Pragma("unroll") for (int i = 0; i < MI; ++i) {                                            \
+        const float* src = &as_[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8];          \
+        float v[8];                                                                               \
+        *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(src);                \
+        *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(src + 4);            \
+        split_bf16(v, ahi[i], alo[i]);                                                            \
+      }                                                                                           \
+      _Pragma("unroll") for (int j = 0; j < NI; ++j) {                                            \
+        const int n = wn * CW + j * 16 + lane % 16;                                               \
+        const int nb = n * LDBS + NQ_GEMM_SWZ(n, lane / 16) * 8;                                  \
+        const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&bs_[nb]);                            \
+        const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&bs_[NP * LDBS + nb]);                \
+        _Pragma("unroll") for (int i = 0; i < MI; ++i) {                                          \
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi, acc[i][j], 0, 0, 0);   \
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo, acc[i][j], 0, 0, 0);   \
+          acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi, acc[i][j], 0, 0, 0);   \
+        }                                                                                         \
+      }                                                                                           \
+    } else {                                                                                      \
+      _Pragma("unroll") for (int kk = 0; kk < BK; kk += 4) {                                      \
+        float a[MI];                                                                              \
+        _Pragma("unroll") for (int i = 0; i < MI; ++i) a[i] =                                     \
+            as_[(wm * RW + i * 16 + lane % 16) * LDA + kk + lane / 16];                           \
+        _Pragma("unroll") for (int j = 0; j < NI; ++j) {                                          \
+          const float b = bs_[(wn * CW + j * 16 + lane % 16) * LDBS + kk + lane / 16];            \
+          _Pragma("unroll") for (int i = 0; i < MI; ++i) acc[i][j] =                              \
+              __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);                  \
+        }                                                                                         \
+      }                                                                                           \
+    }                                                                                             \
+  }
   NQ_GEMM_FETCH_A(0);
   NQ_GEMM_FETCH_B(0);
+  // store, barrier, fetch the next step, products, barrier (a second LDS
+  // buffer with one barrier per step was measured no faster: it halves the
+  // workgroups resident per CU)
   for (int st = 0; st < nsteps; ++st) {
-#pragma unroll
-      for (int q = 0; q < NA; ++q) {
-        const int idx = tid + 256 * q;
-        if (idx < A4) {
-          const int rr = idx / (BK / 4), kk = (idx % (BK / 4)) * 4;
-          const float4 v = ld.finish(ra[q], r0 + rr < nrows, st * BK + kk, rd[q]);
-          if constexpr (sizeof(AT) == 4) {  // one 16-byte LDS store per float4
-            *reinterpret_cast<float4*>(&As[rr * LDA + kk]) = v;
-          } else {                          // four BF16 in one 8-byte store
-            typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
-            bf16x4 b4;
-            b4[0] = (bf16)v.x;
-            b4[1] = (bf16)v.y;
-            b4[2] = (bf16)v.z;
-            b4[3] = (bf16)v.w;
-            *reinterpret_cast<bf16x4*>(&As[rr * LDA + kk]) = b4;
-          }
-        }
-      }
-#pragma unroll
-      for (int q = 0; q < NB; ++q) {
-        const int idx = tid + 256 * q;
-        if (idx < B16) {
-          const int h = idx / (NP * CPR), rem = idx % (NP * CPR);
-          const int n = rem / CPR, ch = rem % CPR;
-          *reinterpret_cast<u32x4*>(&Bs[(h * NP + n) * LDB + ch * EPC]) = rb[q];
-        }
-      }
-      __syncthreads();
-      if (st + 1 < nsteps) {
-        NQ_GEMM_FETCH_A((st + 1) * BK);
-        NQ_GEMM_FETCH_B((st + 1) * BK);
-      }
-      if constexpr (KIND == G_BF16) {
-        bf16x8 a[MI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i)
-          a[i] = *reinterpret_cast<const bf16x8*>(&As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8]);
-#pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          const bf16x8 b =
-              *reinterpret_cast<const bf16x8*>(&Bs[(wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8]);
-#pragma unroll
-          for (int i = 0; i < MI; ++i)
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b, acc[i][j], 0, 0, 0);
-        }
-      } else if constexpr (KIND == G_BF16X3) {
-        bf16x8 ahi[MI], alo[MI];
-#pragma unroll
-        for (int i = 0; i < MI; ++i) {
-          const float* src = &As[(wm * RW + i * 16 + lane % 16) * LDA + (lane / 16) * 8];
-          float v[8];
-          *reinterpret_cast<float4*>(&v[0]) = *reinterpret_cast<const float4*>(src);
-          *reinterpret_cast<float4*>(&v[4]) = *reinterpret_cast<const float4*>(src + 4);
-          split_bf16(v, ahi[i], alo[i]);
-        }
-#pragma unroll
-        for (int j = 0; j < NI; ++j) {
-          const int nb = (wn * CW + j * 16 + lane % 16) * LDB + (lane / 16) * 8;
-          const bf16x8 bhi = *reinterpret_cast<const bf16x8*>(&Bs[nb]);
-          const bf16x8 blo = *reinterpret_cast<const bf16x8*>(&Bs[NP * LDB + nb]);
-#pragma unroll
-          for (int i = 0; i < MI; ++i) {
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo[i], bhi, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], blo, acc[i][j], 0, 0, 0);
-            acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi[i], bhi, acc[i][j], 0, 0, 0);
-          }
-        }
-      } else {
-#pragma unroll
-        for (int kk = 0; kk < BK; kk += 4) {
-          float a[MI];
-#pragma unroll
-          for (int i = 0; i < MI; ++i) a[i] = As[(wm * RW + i * 16 + lane % 16) * LDA + kk + lane / 16];
-#pragma unroll
-          for (int j = 0; j < NI; ++j) {
-            const float b = Bs[(wn * CW + j * 16 + lane % 16) * LDB + kk + lane / 16];
-#pragma unroll
-            for (int i = 0; i < MI; ++i) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x4f32(a[i], b, acc[i][j], 0, 0, 0);
-          }
-        }
-      }
-      __syncthreads();
+    NQ_GEMM_STORE(st);
+    __syncthreads();
+    if (st + 1 < nsteps) {
+      NQ_GEMM_FETCH_A((st + 1) * BK);
+      NQ_GEMM_FETCH_B((st + 1) * BK);
+    }
+    NQ_GEMM_COMPUTE();
+    __syncthreads();
   }
+#undef NQ_GEMM_STORE
+#undef NQ_GEMM_COMPUTE
+#undef NQ_GEMM_SWZ
 #undef NQ_GEMM_FETCH_A
 #undef NQ_GEMM_FETCH_B
   if (ld.gu) {

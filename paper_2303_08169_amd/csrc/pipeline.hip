@@ -1004,10 +1004,10 @@ void launch_gemm_t(hipStream_t s, int64_t cap, int Kp, const void* Bt, const int
 }
 
 // Tile-shape candidates per output width NP: (rows per workgroup BM, wave grid
-// WM x WN). Variant 0 is the default; the autotuner (nq_autotune) times all of
-// them on the real shapes and keeps the fastest per product. Shapes whose LDS
-// (A and B tiles) would not fit are left out for the split-BF16 kind, which
-// keeps both weight halves in LDS.
+// WM x WN). Variant 0 is the default; the
+// autotuner (nq_autotune) times all of them on the real shapes and keeps the
+// fastest per product. Shapes whose LDS (A and B tiles) would not fit are left
+// out for the split-BF16 kind, which keeps both weight halves in LDS.
 int gemm_variants(int kind, int NP) {
   const bool x3 = kind == G_BF16X3;
   switch (NP) {
