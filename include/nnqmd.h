@@ -207,6 +207,18 @@ nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, in
 nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
                           int64_t cap, int64_t* rows, int64_t* width);
 
+/* Kernel choice for the matrix-core products of later evaluations on this
+ * context: NQ_VARIANT_TUNED (default) uses the model's autotuned choice (or
+ * variant 0 before nq_autotune), NQ_VARIANT_LAST the last variant of every
+ * product (the weight-stationary kernel where one is compiled for the
+ * product's shape), and v >= 0 variant v modulo each product's count. The
+ * energies and forces are bitwise identical for every choice; this exists for
+ * tests and measurements. NQ_ERR_ARG for other values. Synchronises the
+ * stream and drops the captured MD graph. */
+#define NQ_VARIANT_TUNED (-1)
+#define NQ_VARIANT_LAST (-2)
+nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant);
+
 /* Upper bound (bytes) of device memory for the per-edge activations of one
  * evaluation (default 160 GiB, further capped at 3/4 of the free memory). When
  * the activations of all edges do not fit, centres are processed in chunks of

@@ -540,6 +540,19 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
   });
 }
 
+nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && variant >= NQ_VARIANT_LAST, NQ_ERR_ARG, "bad kernel variant");
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->user_variant = variant;
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+      ctx->graph_key.clear();
+    }
+  });
+}
+
 nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes) {
   return guarded(ctx, [&] {
     NQ_REQUIRE(ctx && bytes > 0, NQ_ERR_ARG, "bad budget");
@@ -569,9 +582,11 @@ nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int
     const bool was_timing = ctx->timing;
     std::map<std::string, std::vector<double>> ms;  // site -> mean ms per variant
     int nvar = 1;
-    for (const auto& kv : ctx->site_np) nvar = std::max(nvar, gemm_variant_count(model->dims.prec, kv.second));
-    nvar = std::max(nvar, 4);
     try {
+      // one evaluation records the products and their kernel variants
+      ctx->timing = false;
+      evaluate_async(ctx, model, pos, species, n, E, F, nullptr);
+      for (const auto& kv : ctx->site_nvar) nvar = std::max(nvar, kv.second);
       for (int v = 0; v < nvar; ++v) {
         ctx->force_variant = v;
         ctx->timing = false;
@@ -602,7 +617,7 @@ nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int
     bool first = true;
     for (const auto& kv : ms) {
       const int np = ctx->site_np[kv.first];
-      const int nv = gemm_variant_count(model->dims.prec, np);
+      const int nv = ctx->site_nvar[kv.first];
       int best = 0;
       for (int v = 1; v < nv && v < (int)kv.second.size(); ++v)
         if (kv.second[v] < kv.second[best]) best = v;

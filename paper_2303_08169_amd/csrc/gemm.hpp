@@ -29,6 +29,24 @@ __device__ inline float dsiluf(float a) {
 
 constexpr float kInvSqrt2 = 0.70710678118654752f;
 
+// Element operations shared by the product kernels, written with explicit
+// fused multiply-adds so that every kernel rounds them the same way (the
+// compiler would otherwise contract them differently in different contexts).
+// Adjoint of SiLU scaled by f: g f SiLU'(a), with s = sigmoid(a).
+__device__ inline float gradsilu_scale(float g, float a, float s, float f) {
+  return g * (f * s * __builtin_fmaf(a, 1.f - s, 1.f));
+}
+// Row-scale derivative share of four values: sum g SiLU(a).
+__device__ inline float gradsilu_part(const float4& g, const float4& a, float sx, float sy, float sz, float sw) {
+  float p = (g.x * a.x) * sx;
+  p = __builtin_fmaf(g.y * a.y, sy, p);
+  p = __builtin_fmaf(g.z * a.z, sz, p);
+  return __builtin_fmaf(g.w * a.w, sw, p);
+}
+// Residual update (x + u SiLU(y)) / sqrt 2 and its adjoint g / sqrt 2 + y.
+__device__ inline float residual_update(float x, float u, float y) { return __builtin_fmaf(u, siluf(y), x) * kInvSqrt2; }
+__device__ inline float residual_adjoint(float g, float y) { return __builtin_fmaf(g, kInvSqrt2, y); }
+
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 enum ALoadMode { A_PLAIN = 0, A_SILU = 1, A_CAT = 2, A_GRADSILU = 3 };
@@ -52,7 +70,9 @@ struct ALoad {
   // leading dimensions are multiples of 4, so each access is one aligned
   // 16-byte load). r must be a valid row; a column beyond the source width
   // reads column 0 and is zeroed by finish(). Only uniform branches, so the
-  // loads of several K steps can be in flight together.
+  // loads of several K steps can be in flight together. NG: the mode is known
+  // not to be A_GRADSILU (its extra registers are then not needed).
+  template <bool NG = false>
   __device__ inline void fetch(int64_t r, int k, ARaw& o) const {
     if (mode == A_CAT) {
       const bool second = k >= K0;
@@ -62,7 +82,7 @@ struct ALoad {
     } else {
       const int kk = k < K0 ? k : 0;
       o.v = *reinterpret_cast<const float4*>(p0 + r * ld0 + kk);
-      if (mode == A_GRADSILU) {
+      if (!NG && mode == A_GRADSILU) {
         o.a = *reinterpret_cast<const float4*>(p1 + r * ld1 + kk);
         o.f = rs ? rs[r * rs_ld] : 1.f;
       }
@@ -72,6 +92,7 @@ struct ALoad {
   // SiLU, or the adjoint g * c * rowscale * SiLU'(a).
   // With gu set, rd accumulates this chunk's share of sum_k g SiLU(a), the
   // derivative with respect to the row scale, from the same loaded values.
+  template <bool NG = false>
   __device__ inline float4 finish(const ARaw& o, bool row_ok, int k, float& rd) const {
     const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
     float4 v = o.v;
@@ -80,17 +101,17 @@ struct ALoad {
       v.y = siluf(v.y);
       v.z = siluf(v.z);
       v.w = siluf(v.w);
-    } else if (mode == A_GRADSILU) {
+    } else if (!NG && mode == A_GRADSILU) {
       const float f = c * o.f;
       const float sx = sigmoidf_(o.a.x), sy = sigmoidf_(o.a.y), sz = sigmoidf_(o.a.z), sw = sigmoidf_(o.a.w);
       if (gu) {
-        const float part = v.x * o.a.x * sx + v.y * o.a.y * sy + v.z * o.a.z * sz + v.w * o.a.w * sw;
+        const float part = gradsilu_part(v, o.a, sx, sy, sz, sw);
         rd += ok ? part : 0.f;
       }
-      v.x *= f * sx * (1.f + o.a.x * (1.f - sx));
-      v.y *= f * sy * (1.f + o.a.y * (1.f - sy));
-      v.z *= f * sz * (1.f + o.a.z * (1.f - sz));
-      v.w *= f * sw * (1.f + o.a.w * (1.f - sw));
+      v.x = gradsilu_scale(v.x, o.a.x, sx, f);
+      v.y = gradsilu_scale(v.y, o.a.y, sy, f);
+      v.z = gradsilu_scale(v.z, o.a.z, sz, f);
+      v.w = gradsilu_scale(v.w, o.a.w, sw, f);
     }
     return ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
   }
@@ -168,10 +189,10 @@ __device__ inline void store_tiles(const Epi& ep, const floatx4 (&acc)[MI][NI], 
             o1[c] = rsv[q] * siluf(v);
           } else if constexpr (MODE == E_RESIDUAL) {
             o0[c] = v;
-            o1[c] = (in[jj][q] + rsv[q] * siluf(v)) * kInvSqrt2;
+            o1[c] = residual_update(in[jj][q], rsv[q], v);
           } else if constexpr (MODE == E_LATENT_BWD) {
             if (c < ep.D)
-              o0[c] = in[jj][q] * kInvSqrt2 + v;
+              o0[c] = residual_adjoint(in[jj][q], v);
             else
               o1[c - ep.D] = v;
           } else {
@@ -412,5 +433,247 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
     default: store_tiles<E_ADD>(ep, acc, rbase, cbase, lane, nrows); break;
   }
 }
+
+// Weight-stationary persistent variant for the BF16 kinds. One workgroup of
+// 8 wavefronts per CU keeps the whole weight matrix in registers as
+// matrix-core B fragments (wavefront w owns the NTW 16-column output tiles
+// starting at column 16 NTW w, for all KS K steps), so no weight tile is
+// staged through LDS again; workgroups then loop over 16-row edge tiles. The
+// A tile of the next row tile is loaded into registers while the current one
+// is multiplied from LDS (two LDS buffers, one barrier per row tile). The A
+// tile is split into its BF16 halves once, when written to LDS, instead of by
+// every wavefront that reads it. K steps, the split and the product order per
+// step are those of k_gemm, so the products are bitwise identical to it.
+// Loader and epilogue modes are compile-time, and every global address is a
+// per-tile uniform base plus a 32-bit lane offset, which keeps the registers
+// beside the weights within budget. The residual update and the latent
+// adjoint read their FP32 inputs (x, the first D columns of [x | s]; the raw
+// g rows) from a third LDS tile, so those epilogues do no global loads that
+// could alias their stores.
+// With ld.gu set, Kp must be 256: one wavefront's load then covers one row
+// (eight K steps of eight chunks).
+template <int KIND, int NTW, int KS, int AMODE, int EMODE>
+__global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict__ Bt, const int* __restrict__ nrows_p,
+                                                 ALoad ld, Epi ep) {
+  static_assert(KIND == G_BF16 || KIND == G_BF16X3, "BF16 kinds only");
+  constexpr int H = KIND == G_BF16X3 ? 2 : 1;  // weight halves (hi, lo)
+  constexpr int RT = 16;                       // rows per tile
+  constexpr int Kp = KS * 32;
+  constexpr int LDH = Kp + 8;                  // LDS row stride of the BF16 halves
+  constexpr int LDW = Kp + 4;                  // ... of the FP32 copy
+  constexpr int CPR = Kp / 4;                  // float4 chunks per row
+  constexpr int A4 = RT * CPR;                 // ... per tile
+  constexpr int NA = (A4 + 511) / 512;
+  constexpr bool GR = AMODE == A_GRADSILU;
+  constexpr bool XIN = EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD;  // FP32 copy of the primary source
+  __shared__ __attribute__((aligned(16))) bf16 As[2][H * RT * LDH];
+  __shared__ __attribute__((aligned(16))) float Xs[XIN ? 2 : 1][XIN ? RT * LDW : 4];
+  const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
+  const int64_t nrows = *nrows_p;
+  const int64_t ntiles = (nrows + RT - 1) / RT;
+  const int nt = NP / 16;
+  const int my0 = __builtin_amdgcn_readfirstlane(wave * NTW);
+  const int my_nt = my0 >= nt ? 0 : (nt - my0 < NTW ? nt - my0 : NTW);
+
+  bf16x8 bw[NTW][KS][H];
+#pragma unroll
+  for (int j = 0; j < NTW; ++j)
+#pragma unroll
+    for (int s = 0; s < KS; ++s)
+#pragma unroll
+      for (int h = 0; h < H; ++h) {
+        bf16x8 z;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) z[e] = (bf16)0.f;
+        if (j < my_nt)
+          z = *reinterpret_cast<const bf16x8*>(Bt + (int64_t)h * NP * Kp + ((my0 + j) * 16 + lane % 16) * Kp + s * 32 +
+                                               (lane / 16) * 8);
+        bw[j][s][h] = z;
+      }
+
+  // staged raw A values of one row tile (chunk q: row idx / CPR, columns
+  // 4 (idx % CPR) .. +3 with idx = tid + 512 q)
+  float4 rv[NA], rg[GR ? NA : 1];
+  float rf[GR ? NA : 1];
+  auto fetch = [&](int64_t tile, int t) {
+    const int64_t row0 = tile * RT;
+    const int lim = (int)(nrows - 1 - row0 < RT ? nrows - 1 - row0 : RT - 1);
+    const float* b0 = ld.p0 + row0 * ld.ld0;
+    const float* b1 = ld.p1 + row0 * ld.ld1;
+    // without a row scale the (unused) scale load reads a valid address
+    const float* brs = ld.rs ? ld.rs + row0 * ld.rs_ld : ld.p1;
+    const int rsl = ld.rs ? ld.rs_ld : 0;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int idx = (t + 512 * q) % A4;
+      const int r = idx / CPR < lim ? idx / CPR : lim;
+      const int k = (idx % CPR) * 4;
+      if constexpr (AMODE == A_CAT) {
+        const float* p = k >= ld.K0 ? b1 + (unsigned)(r * ld.ld1 + (k - ld.K0 < ld.K1 ? k - ld.K0 : 0))
+                                    : b0 + (unsigned)(r * ld.ld0 + k);
+        rv[q] = *reinterpret_cast<const float4*>(p);
+      } else {
+        const int kk = k < ld.K0 ? k : 0;
+        rv[q] = *reinterpret_cast<const float4*>(b0 + (unsigned)(r * ld.ld0 + kk));
+        if constexpr (GR) {
+          rg[q] = *reinterpret_cast<const float4*>(b1 + (unsigned)(r * ld.ld1 + kk));
+          rf[q] = brs[(unsigned)(r * rsl)];
+        }
+      }
+    }
+  };
+  auto store = [&](int64_t tile, bf16* dst, float* xdst, int t) {
+    const int64_t row0 = tile * RT;
+#pragma unroll
+    for (int q = 0; q < NA; ++q) {
+      const int idx = t + 512 * q;
+      const int i2 = idx % A4, rr = i2 / CPR, k = (i2 % CPR) * 4;
+      const bool ok = row0 + rr < nrows && k < (AMODE == A_CAT ? ld.K0 + ld.K1 : ld.K0);
+      float4 v = rv[q];
+      if constexpr (XIN)
+        if (idx < A4 && k < ld.K0)
+          *reinterpret_cast<float4*>(&xdst[rr * LDW + k]) = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
+      float rd = 0.f;
+      if constexpr (AMODE == A_SILU) {
+        v.x = siluf(v.x);
+        v.y = siluf(v.y);
+        v.z = siluf(v.z);
+        v.w = siluf(v.w);
+      } else if constexpr (GR) {
+        const float4 a = rg[q];
+        const float f = ld.c * (ld.rs ? rf[q] : 1.f);
+        const float sx = sigmoidf_(a.x), sy = sigmoidf_(a.y), sz = sigmoidf_(a.z), sw = sigmoidf_(a.w);
+        rd = ok ? gradsilu_part(v, a, sx, sy, sz, sw) : 0.f;
+        v.x = gradsilu_scale(v.x, a.x, sx, f);
+        v.y = gradsilu_scale(v.y, a.y, sy, f);
+        v.z = gradsilu_scale(v.z, a.z, sz, f);
+        v.w = gradsilu_scale(v.w, a.w, sw, f);
+      }
+      if (idx < A4) {
+        typedef __bf16 bf16x4 __attribute__((ext_vector_type(4)));
+        const float e[4] = {ok ? v.x : 0.f, ok ? v.y : 0.f, ok ? v.z : 0.f, ok ? v.w : 0.f};
+        bf16x4 hi, lo;
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          hi[u] = (bf16)e[u];
+          lo[u] = (bf16)(e[u] - (float)hi[u]);
+        }
+        *reinterpret_cast<bf16x4*>(&dst[rr * LDH + k]) = hi;
+        if constexpr (H == 2) *reinterpret_cast<bf16x4*>(&dst[RT * LDH + rr * LDH + k]) = lo;
+      }
+      if (GR && ld.gu && 512 * q + wave * 64 < A4) {
+        // the 64 lanes hold the row's chunks in order; sum them as k_gemm
+        // does (per 8-lane group sequentially over its 8 K steps, then across
+        // the group), so dE/du is bitwise identical too
+        float r8 = 0.f;
+#pragma unroll
+        for (int s = 0; s < 8; ++s) r8 += __shfl(rd, s * 8 + (lane & 7));
+#pragma unroll
+        for (int o = 1; o < 8; o <<= 1) r8 += __shfl_xor(r8, o);
+        if (lane == 0 && row0 + rr < nrows) ld.gu[row0 + rr] += ld.c * r8;
+      }
+    }
+  };
+
+  int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  fetch(tile, tid);
+  store(tile, As[0], Xs[0], tid);
+  if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x, tid);
+  __syncthreads();
+  for (int it = 0; tile < ntiles; ++it, tile += gridDim.x) {
+    // The lane-dependent offsets below are loop-invariant; recomputing them
+    // from an opaque copy of the thread index each iteration is cheaper than
+    // the registers that hoisting them out of the loop would take.
+    int t = tid;
+    asm volatile("" : "+v"(t));
+    const int ln = t % 64;
+    const bf16* a_ = As[it & 1] + (ln % 16) * LDH + (ln / 16) * 8;
+    floatx4 acc[NTW];
+#pragma unroll
+    for (int j = 0; j < NTW; ++j) acc[j] = floatx4{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int s = 0; s < KS; ++s) {
+      // tiles a wavefront does not own hold zero weights: no branches here
+      const bf16x8 ahi = *reinterpret_cast<const bf16x8*>(a_ + s * 32);
+      if constexpr (KIND == G_BF16X3) {
+        const bf16x8 alo = *reinterpret_cast<const bf16x8*>(a_ + RT * LDH + s * 32);
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(alo, bw[j][s][0], acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][H - 1], acc[j], 0, 0, 0);
+          acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][0], acc[j], 0, 0, 0);
+        }
+      } else {
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][0], acc[j], 0, 0, 0);
+      }
+    }
+    // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each tile
+    {
+      const int64_t row0 = tile * RT;
+      const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+      float* o0b = ep.o0 + row0 * ep.ld0;
+      float* o1b = ep.o1 + row0 * ep.ld1;
+      const float* rsb = ep.rs + row0 * ep.rs_ld;
+      const float* lin = Xs[XIN ? it & 1 : 0];
+      float rsv[4], in[4][NTW];
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = (ln / 16) * 4 + q;
+        const int rc = r < nvalid ? r : nvalid - 1;
+        if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL) rsv[q] = rsb[(unsigned)(rc * ep.rs_ld)];
+        if constexpr (EMODE == E_ADD) {
+#pragma unroll
+          for (int j = 0; j < NTW; ++j) {
+            const int c = (my0 + j) * 16 + ln % 16;
+            in[q][j] = o0b[(unsigned)(rc * ep.ld0 + (c < ep.N0 ? c : 0))];
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int r = (ln / 16) * 4 + q;
+        if (r >= nvalid) continue;
+#pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+          const int c = (my0 + j) * 16 + ln % 16;
+          if (j >= my_nt || c >= ep.N0) continue;
+          const float v = acc[j][q];
+          float* o0 = o0b + (unsigned)(r * ep.ld0 + c);
+          if constexpr (EMODE == E_STORE) {
+            *o0 = v;
+          } else if constexpr (EMODE == E_STORE_X0) {
+            *o0 = v;
+            o1b[(unsigned)(r * ep.ld1 + c)] = rsv[q] * siluf(v);
+          } else if constexpr (EMODE == E_RESIDUAL) {
+            *o0 = v;
+            o1b[(unsigned)(r * ep.ld1 + c)] = residual_update(lin[r * LDW + c], rsv[q], v);
+          } else if constexpr (EMODE == E_LATENT_BWD) {
+            if (c < ep.D)
+              *o0 = residual_adjoint(lin[r * LDW + c], v);
+            else
+              o1b[(unsigned)(r * ep.ld1 + c - ep.D)] = v;
+          } else {
+            *o0 = in[q][j] + v;
+          }
+        }
+      }
+    }
+    // the next tile into the other buffer (last read before the previous
+    // barrier), after the epilogue so the accumulators are no longer live
+    const int64_t next = tile + gridDim.x;
+    if (next < ntiles) {
+      store(next, As[(it + 1) & 1], Xs[XIN ? (it + 1) & 1 : 0], t);
+      if (next + gridDim.x < ntiles) fetch(next + gridDim.x, t);
+    }
+    __syncthreads();
+  }
+}
+
+// Weight-stationary launch of one product (gemm_ws.hip). Returns whether the
+// product's signature has a compiled kernel; launches it only when asked.
+bool gemm_ws(bool launch, int kind, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt, const int* nrows,
+             const ALoad& ld, const Epi& ep);
 
 }  // namespace nq

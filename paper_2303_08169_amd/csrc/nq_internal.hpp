@@ -199,7 +199,9 @@ struct nq_ctx {
   // per-launch timing with HIP events on the context's stream
   bool timing = false;
   int force_variant = -1;               // >= 0 while the autotuner times one tile shape
+  int user_variant = NQ_VARIANT_TUNED;  // nq_ctx_set_variant
   std::map<std::string, int> site_np;   // output width of each named matrix-core product
+  std::map<std::string, int> site_nvar; // kernel variants available for it
   std::vector<nq::Span> spans;
   std::vector<hipEvent_t> event_pool;
 };
@@ -229,7 +231,6 @@ void backward_async(nq_ctx* ctx, const nq_model* m);
 void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep = 1,
                   int64_t n_centres = -1);
 
-int gemm_variant_count(int prec, int NP);
 
 // ---- MD (md.hip)
 void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass,

@@ -1071,7 +1071,7 @@ void launch_gemm_np(hipStream_t s, int64_t cap, int NP, int Kp, const void* Bt, 
 }
 
 // Algorithmic HBM bytes per edge row of one product: every source value of A
-// read once, every value the epilogue reads or writes once.
+// read once, every other value the epilogue reads or writes once.
 double gemm_bytes_per_row(const ALoad& ld, const Epi& ep) {
   double a = 0;
   switch (ld.mode) {
@@ -1083,15 +1083,17 @@ double gemm_bytes_per_row(const ALoad& ld, const Epi& ep) {
   switch (ep.mode) {
     case E_STORE: o = ep.N0; break;
     case E_STORE_X0: o = 2.0 * ep.N0 + 1; break;
-    case E_RESIDUAL: o = 3.0 * ep.N0 + 1; break;
-    case E_LATENT_BWD: o = ep.D + ep.N0; break;
+    case E_RESIDUAL: o = 2.0 * ep.N0 + 1; break;  // x is the first part of A
+    case E_LATENT_BWD: o = ep.N0; break;          // g is A's source
     default: o = 2.0 * ep.N0;
   }
   return 4.0 * (a + o);
 }
 
-// y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map. The tile shape
-// is the model's tuned choice for this product (or the one being timed).
+// y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map. The kernel is
+// the model's tuned choice for this product (or the one being timed): one of
+// the tile shapes of k_gemm or, where compiled, the weight-stationary k_gemm_ws
+// (the last variant).
 void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep,
           const std::string& name) {
   const Workspace& ws = ctx->ws;
@@ -1103,17 +1105,33 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
   int v = 0;
   if (ctx->force_variant >= 0) {
     v = ctx->force_variant;
-  } else {
+  } else if (ctx->user_variant >= 0) {
+    v = ctx->user_variant;
+  } else if (ctx->user_variant == NQ_VARIANT_TUNED) {
     auto it = m->gemm_choice.find(name);
     if (it != m->gemm_choice.end()) v = it->second;
   }
+  const int kind = m->dims.prec == NQ_PRECISION_BF16X3 ? G_BF16X3
+                   : (m->dims.prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32);
+  const void* Bbf = (bwd ? L.bf_bwd : L.bf_fwd).p;
+  const int ntile = gemm_variants(kind, NP);
+  const bool has_ws = gemm_ws(false, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
+  const int nv = ntile + (has_ws ? 1 : 0);
   ctx->site_np[name] = NP;
+  ctx->site_nvar[name] = nv;
+  v = ctx->force_variant < 0 && ctx->user_variant == NQ_VARIANT_LAST ? nv - 1 : v % nv;
+  if (has_ws && v == ntile) {
+    gemm_ws(true, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
+    NQ_HIP(hipGetLastError());
+    span_end(ctx, sp);
+    return;
+  }
   switch (m->dims.prec) {
     case NQ_PRECISION_BF16:
-      launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep, v);
+      launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, Bbf, nr, ld, ep, v);
       break;
     case NQ_PRECISION_BF16X3:
-      launch_gemm_np<G_BF16X3>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.bf_bwd : L.bf_fwd).p, nr, ld, ep, v);
+      launch_gemm_np<G_BF16X3>(ctx->stream, ws.cap, NP, Kp, Bbf, nr, ld, ep, v);
       break;
     default:
       launch_gemm_np<G_F32>(ctx->stream, ws.cap, NP, Kp, (bwd ? L.f32_bwd : L.f32_fwd).p, nr, ld, ep, v);
@@ -1121,14 +1139,6 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
   NQ_HIP(hipGetLastError());
   span_end(ctx, sp);
 }
-
-}  // namespace
-
-int gemm_variant_count(int prec, int NP) {
-  return gemm_variants(prec == NQ_PRECISION_BF16X3 ? G_BF16X3 : (prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32), NP);
-}
-
-namespace {
 
 ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }
 ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }

@@ -182,6 +182,12 @@ class Potential:
                                      int(reps), buf, len(buf), C.byref(n)), self._ctx)
         return json.loads(buf.value.decode())
 
+    def set_variant(self, variant: int):
+        """Kernel choice of the matrix-core products: -1 tuned (default), -2 the
+        last variant of each product (weight-stationary where compiled), v >= 0
+        variant v of each. Results are bitwise identical for every choice."""
+        B.check(self.lib.nq_ctx_set_variant(self._ctx, int(variant)), self._ctx)
+
     def set_workspace_budget(self, nbytes: int):
         """Cap the per-edge activation memory; larger systems run in chunks of centres."""
         B.check(self.lib.nq_ctx_set_workspace_budget(self._ctx, int(nbytes)), self._ctx)
