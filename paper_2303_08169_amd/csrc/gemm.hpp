@@ -434,6 +434,22 @@ __global__ __launch_bounds__(256) void k_gemm(int Kp, const typename GemmTraits<
   }
 }
 
+// Raw buffer resource over [base, base + bytes): loads beyond it return 0 and
+// stores beyond it are dropped by the hardware, which lets a kernel guard
+// its memory operations by offset instead of by branches.
+__device__ inline __amdgpu_buffer_rsrc_t buffer_rsrc(const void* base, int64_t bytes) {
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), (short)0, (int)bytes, 0x00020000);
+}
+constexpr unsigned kOutOfRange = 0x80000000u;
+// 32-bit buffer load / store of a float at a byte offset (the builtins move
+// raw 32-bit words).
+__device__ inline float buf_load(__amdgpu_buffer_rsrc_t r, unsigned off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, off, 0, 0));
+}
+__device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off) {
+  __builtin_amdgcn_raw_buffer_store_b32(__builtin_bit_cast(unsigned, v), r, off, 0, 0);
+}
+
 // Weight-stationary persistent variant for the BF16 kinds. One workgroup of
 // 8 wavefronts per CU keeps the whole weight matrix in registers as
 // matrix-core B fragments (wavefront w owns the NTW 16-column output tiles
@@ -468,6 +484,8 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
   constexpr bool XIN = EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD;  // FP32 copy of the primary source
   __shared__ __attribute__((aligned(16))) bf16 As[2][H * RT * LDH];
   __shared__ __attribute__((aligned(16))) float Xs[XIN ? 2 : 1][XIN ? RT * LDW : 4];
+  constexpr bool RS = EMODE == E_STORE_X0 || EMODE == E_RESIDUAL;  // epilogue row scale, staged too
+  __shared__ float Us[2][RT];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int64_t nrows = *nrows_p;
   const int64_t ntiles = (nrows + RT - 1) / RT;
@@ -494,7 +512,7 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
   // staged raw A values of one row tile (chunk q: row idx / CPR, columns
   // 4 (idx % CPR) .. +3 with idx = tid + 512 q)
   float4 rv[NA], rg[GR ? NA : 1];
-  float rf[GR ? NA : 1];
+  float rf[GR ? NA : 1], ru = 0.f;
   auto fetch = [&](int64_t tile, int t) {
     const int64_t row0 = tile * RT;
     const int lim = (int)(nrows - 1 - row0 < RT ? nrows - 1 - row0 : RT - 1);
@@ -503,6 +521,7 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
     // without a row scale the (unused) scale load reads a valid address
     const float* brs = ld.rs ? ld.rs + row0 * ld.rs_ld : ld.p1;
     const int rsl = ld.rs ? ld.rs_ld : 0;
+    if constexpr (RS) ru = ep.rs[(row0 + (t % RT < lim ? t % RT : lim)) * ep.rs_ld];
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int idx = (t + 512 * q) % A4;
@@ -522,8 +541,9 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
       }
     }
   };
-  auto store = [&](int64_t tile, bf16* dst, float* xdst, int t) {
+  auto store = [&](int64_t tile, bf16* dst, float* xdst, float* udst, int t) {
     const int64_t row0 = tile * RT;
+    if (RS && t < RT) udst[t] = ru;
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int idx = t + 512 * q;
@@ -561,7 +581,7 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
         *reinterpret_cast<bf16x4*>(&dst[rr * LDH + k]) = hi;
         if constexpr (H == 2) *reinterpret_cast<bf16x4*>(&dst[RT * LDH + rr * LDH + k]) = lo;
       }
-      if (GR && ld.gu && 512 * q + wave * 64 < A4) {
+      if constexpr (GR && KS == 8) {  // (the launcher passes gu only when Kp = 256)
         // the 64 lanes hold the row's chunks in order; sum them as k_gemm
         // does (per 8-lane group sequentially over its 8 K steps, then across
         // the group), so dE/du is bitwise identical too
@@ -570,7 +590,12 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
         for (int s = 0; s < 8; ++s) r8 += __shfl(rd, s * 8 + (lane & 7));
 #pragma unroll
         for (int o = 1; o < 8; o <<= 1) r8 += __shfl_xor(r8, o);
-        if (lane == 0 && row0 + rr < nrows) ld.gu[row0 + rr] += ld.c * r8;
+        // one lane adds the row's sum; without gu the buffer is empty
+        const __amdgpu_buffer_rsrc_t G =
+            buffer_rsrc(ld.gu ? ld.gu + row0 : nullptr, ld.gu ? (nrows - row0 < RT ? nrows - row0 : RT) * 4 : 0);
+        const unsigned off = lane == 0 ? (unsigned)rr * 4 : kOutOfRange;
+        const float g0 = buf_load(G, off);
+        buf_store(g0 + ld.c * r8, G, off);
       }
     }
   };
@@ -578,8 +603,11 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
   fetch(tile, tid);
-  store(tile, As[0], Xs[0], tid);
-  if (tile + gridDim.x < ntiles) fetch(tile + gridDim.x, tid);
+  store(tile, As[0], Xs[0], Us[0], tid);
+  // fetches are unconditional (a tile past the end is replaced by the last
+  // one, loaded and never used) so every path issues the same memory
+  // operations and the compiler's wait counts stay exact
+  fetch(tile + gridDim.x < ntiles ? tile + gridDim.x : ntiles - 1, tid);
   __syncthreads();
   for (int it = 0; tile < ntiles; ++it, tile += gridDim.x) {
     // The lane-dependent offsets below are loop-invariant; recomputing them
@@ -609,53 +637,54 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
         for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][0], acc[j], 0, 0, 0);
       }
     }
-    // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each tile
+    // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each
+    // tile; buffer stores drop rows past the end and columns past N0
     {
       const int64_t row0 = tile * RT;
       const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
-      float* o0b = ep.o0 + row0 * ep.ld0;
-      float* o1b = ep.o1 + row0 * ep.ld1;
-      const float* rsb = ep.rs + row0 * ep.rs_ld;
+      const __amdgpu_buffer_rsrc_t R0 = buffer_rsrc(ep.o0 + row0 * ep.ld0, (int64_t)nvalid * ep.ld0 * 4);
+      __amdgpu_buffer_rsrc_t R1 = R0;
+      if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD)
+        R1 = buffer_rsrc(ep.o1 + row0 * ep.ld1, (int64_t)nvalid * ep.ld1 * 4);
       const float* lin = Xs[XIN ? it & 1 : 0];
-      float rsv[4], in[4][NTW];
+      float rsv[4];
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = (ln / 16) * 4 + q;
-        const int rc = r < nvalid ? r : nvalid - 1;
-        if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL) rsv[q] = rsb[(unsigned)(rc * ep.rs_ld)];
+      for (int q = 0; q < 4; ++q) rsv[q] = RS ? Us[it & 1][(ln / 16) * 4 + q] : 0.f;
+#pragma unroll
+      for (int j = 0; j < NTW; ++j) {
+        const int c0 = (my0 + j) * 16;  // first column of the tile (uniform)
+        const int c = c0 + ln % 16;
+        const bool cok = j < my_nt && c < ep.N0;
+        const int cl = cok ? c : 0;  // in-range column for LDS reads
+        float in[4];
         if constexpr (EMODE == E_ADD) {
 #pragma unroll
-          for (int j = 0; j < NTW; ++j) {
-            const int c = (my0 + j) * 16 + ln % 16;
-            in[q][j] = o0b[(unsigned)(rc * ep.ld0 + (c < ep.N0 ? c : 0))];
+          for (int q = 0; q < 4; ++q) {
+            const int r = (ln / 16) * 4 + q;
+            in[q] = buf_load(R0, cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange);
           }
         }
-      }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        const int r = (ln / 16) * 4 + q;
-        if (r >= nvalid) continue;
-#pragma unroll
-        for (int j = 0; j < NTW; ++j) {
-          const int c = (my0 + j) * 16 + ln % 16;
-          if (j >= my_nt || c >= ep.N0) continue;
+        for (int q = 0; q < 4; ++q) {
+          const int r = (ln / 16) * 4 + q;
           const float v = acc[j][q];
-          float* o0 = o0b + (unsigned)(r * ep.ld0 + c);
+          const unsigned off0 = cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange;
+          const unsigned off1 = cok ? (unsigned)(r * ep.ld1 + c) * 4 : kOutOfRange;
           if constexpr (EMODE == E_STORE) {
-            *o0 = v;
+            buf_store(v, R0, off0);
           } else if constexpr (EMODE == E_STORE_X0) {
-            *o0 = v;
-            o1b[(unsigned)(r * ep.ld1 + c)] = rsv[q] * siluf(v);
+            buf_store(v, R0, off0);
+            buf_store(rsv[q] * siluf(v), R1, off1);
           } else if constexpr (EMODE == E_RESIDUAL) {
-            *o0 = v;
-            o1b[(unsigned)(r * ep.ld1 + c)] = residual_update(lin[r * LDW + c], rsv[q], v);
+            buf_store(v, R0, off0);
+            buf_store(residual_update(lin[r * LDW + cl], rsv[q], v), R1, off1);
           } else if constexpr (EMODE == E_LATENT_BWD) {
-            if (c < ep.D)
-              *o0 = residual_adjoint(lin[r * LDW + c], v);
-            else
-              o1b[(unsigned)(r * ep.ld1 + c - ep.D)] = v;
+            // columns below D update g in place, the rest are the scalar adjoint
+            const bool lo = c0 < ep.D;
+            const unsigned off = !cok ? kOutOfRange : lo ? off0 : (unsigned)(r * ep.ld1 + c - ep.D) * 4;
+            buf_store(lo ? residual_adjoint(lin[r * LDW + (lo ? cl : 0)], v) : v, lo ? R0 : R1, off);
           } else {
-            *o0 = in[q][j] + v;
+            buf_store(in[q] + v, R0, off0);
           }
         }
       }
@@ -663,10 +692,9 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
     // the next tile into the other buffer (last read before the previous
     // barrier), after the epilogue so the accumulators are no longer live
     const int64_t next = tile + gridDim.x;
-    if (next < ntiles) {
-      store(next, As[(it + 1) & 1], Xs[XIN ? (it + 1) & 1 : 0], t);
-      if (next + gridDim.x < ntiles) fetch(next + gridDim.x, t);
-    }
+    if (next >= ntiles) break;
+    store(next, As[(it + 1) & 1], Xs[XIN ? (it + 1) & 1 : 0], Us[(it + 1) & 1], t);
+    fetch(next + gridDim.x < ntiles ? next + gridDim.x : ntiles - 1, t);
     __syncthreads();
   }
 }
