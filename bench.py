@@ -343,9 +343,11 @@ def main():
     for mode in modes:
         pot = Potential(cf.model, w, mode)
         if not args.no_autotune:
-            rep = pot.autotune(P, Z, box, reps=2)
+            rep = pot.autotune(P, Z, box, reps=3)
             tuned[mode] = {s["name"]: s["chosen"] for s in rep["sites"]}
-            log(f"{mode}: autotuned tile shapes {tuned[mode]}")
+            log(f"{mode}: autotuned kernel variants {tuned[mode]}")
+            for s_ in rep["sites"]:
+                log(f"   {s_['name']:<16} " + " ".join(f"{t:.3f}" for t in s_["ms"]))
         steps = args.steps if mode == args.precision else max(3, min(args.steps, 10))
         dt, report, ne, E, F = timed_run(pot, P, Z, box, steps, args.warmup if mode == args.precision else 2)
         _, _, Ei = pot.energy_forces(P, Z, box, atom_energy=True)

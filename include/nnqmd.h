@@ -209,14 +209,16 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
 
 /* Kernel choice for the matrix-core products of later evaluations on this
  * context: NQ_VARIANT_TUNED (default) uses the model's autotuned choice (or
- * variant 0 before nq_autotune), NQ_VARIANT_LAST the last variant of every
- * product (the weight-stationary kernel where one is compiled for the
- * product's shape), and v >= 0 variant v modulo each product's count. The
- * energies and forces are bitwise identical for every choice; this exists for
- * tests and measurements. NQ_ERR_ARG for other values. Synchronises the
- * stream and drops the captured MD graph. */
+ * variant 0 before nq_autotune), NQ_VARIANT_LAST and NQ_VARIANT_LAST2 the last
+ * and second-to-last variant of every product (the two epilogue forms of the
+ * weight-stationary kernel where one is compiled for the product's shape), and
+ * v >= 0 variant v modulo each product's count. The energies and forces are
+ * bitwise identical for every choice; this exists for tests and measurements.
+ * NQ_ERR_ARG for other values. Synchronises the stream and drops the captured
+ * MD graph. */
 #define NQ_VARIANT_TUNED (-1)
 #define NQ_VARIANT_LAST (-2)
+#define NQ_VARIANT_LAST2 (-3)
 nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant);
 
 /* Upper bound (bytes) of device memory for the per-edge activations of one

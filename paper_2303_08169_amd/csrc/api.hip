@@ -542,7 +542,7 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
 
 nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant) {
   return guarded(ctx, [&] {
-    NQ_REQUIRE(ctx && variant >= NQ_VARIANT_LAST, NQ_ERR_ARG, "bad kernel variant");
+    NQ_REQUIRE(ctx && variant >= NQ_VARIANT_LAST2, NQ_ERR_ARG, "bad kernel variant");
     NQ_HIP(hipStreamSynchronize(ctx->stream));
     ctx->user_variant = variant;
     if (ctx->graph_exec) {

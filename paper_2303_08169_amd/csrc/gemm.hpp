@@ -468,8 +468,8 @@ __device__ inline void buf_store(float v, __amdgpu_buffer_rsrc_t r, unsigned off
 // could alias their stores.
 // With ld.gu set, Kp must be 256: one wavefront's load then covers one row
 // (eight K steps of eight chunks).
-template <int KIND, int NTW, int KS, int AMODE, int EMODE>
-__global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict__ Bt, const int* __restrict__ nrows_p,
+template <int KIND, int NTW, int KS, int AMODE, int EMODE, int PF, int EPI>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_gemm_ws(int NP, const bf16* __restrict__ Bt, const int* __restrict__ nrows_p,
                                                  ALoad ld, Epi ep) {
   static_assert(KIND == G_BF16 || KIND == G_BF16X3, "BF16 kinds only");
   constexpr int H = KIND == G_BF16X3 ? 2 : 1;  // weight halves (hi, lo)
@@ -486,6 +486,11 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
   __shared__ __attribute__((aligned(16))) float Xs[XIN ? 2 : 1][XIN ? RT * LDW : 4];
   constexpr bool RS = EMODE == E_STORE_X0 || EMODE == E_RESIDUAL;  // epilogue row scale, staged too
   __shared__ float Us[2][RT];
+  constexpr int LDO = 8 * NTW * 16 + 4;  // products of one row tile, all wavefronts' columns
+  constexpr int NE = NTW;                // float4 output chunks per thread (RT * 8 NTW * 16 / 4 / 512)
+  __shared__ __attribute__((aligned(16))) float Os[EPI == 1 ? RT * LDO : 4];
+  constexpr bool ADD = EMODE == E_ADD && EPI == 1;  // the accumulated rows are staged like A
+  __shared__ __attribute__((aligned(16))) float Is[ADD ? 2 : 1][ADD ? RT * LDO : 4];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int64_t nrows = *nrows_p;
   const int64_t ntiles = (nrows + RT - 1) / RT;
@@ -511,9 +516,16 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
 
   // staged raw A values of one row tile (chunk q: row idx / CPR, columns
   // 4 (idx % CPR) .. +3 with idx = tid + 512 q)
-  float4 rv[NA], rg[GR ? NA : 1];
-  float rf[GR ? NA : 1], ru = 0.f;
-  auto fetch = [&](int64_t tile, int t) {
+  struct Stage {
+    float4 rv[NA], rg[GR ? NA : 1], in[ADD ? NE : 1];
+    float rf[GR ? NA : 1], ru;  // ru: the epilogue row scale, or dE/du of rows (wave + 8 lane) (GR)
+  };
+  Stage s0, s1;  // s1 is used only with two tiles in flight (PF = 2)
+  // dE/du of the rows of a tile (empty without gu)
+  auto gu_rsrc = [&](int64_t row0) {
+    return buffer_rsrc(ld.gu ? ld.gu + row0 : nullptr, ld.gu ? (nrows - row0 < RT ? nrows - row0 : RT) * 4 : 0);
+  };
+  auto fetch = [&](int64_t tile, int t, Stage& S) {
     const int64_t row0 = tile * RT;
     const int lim = (int)(nrows - 1 - row0 < RT ? nrows - 1 - row0 : RT - 1);
     const float* b0 = ld.p0 + row0 * ld.ld0;
@@ -521,7 +533,21 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
     // without a row scale the (unused) scale load reads a valid address
     const float* brs = ld.rs ? ld.rs + row0 * ld.rs_ld : ld.p1;
     const int rsl = ld.rs ? ld.rs_ld : 0;
-    if constexpr (RS) ru = ep.rs[(row0 + (t % RT < lim ? t % RT : lim)) * ep.rs_ld];
+    if constexpr (RS) S.ru = ep.rs[(row0 + (t % RT < lim ? t % RT : lim)) * ep.rs_ld];
+    if constexpr (GR && KS == 8) {
+      const int w = t / 64, l = t % 64;
+      S.ru = buf_load(gu_rsrc(row0), l < 2 ? (unsigned)(w + 8 * l) * 4 : kOutOfRange);
+    }
+    if constexpr (ADD) {
+      const int cpr = ep.N0 / 4;
+      const float* bo = ep.o0 + row0 * ep.ld0;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int idx = (t + 512 * e) % (RT * cpr);
+        const int r = idx / cpr < lim ? idx / cpr : lim;
+        S.in[e] = *reinterpret_cast<const float4*>(bo + (unsigned)(r * ep.ld0 + (idx % cpr) * 4));
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int idx = (t + 512 * q) % A4;
@@ -530,26 +556,37 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
       if constexpr (AMODE == A_CAT) {
         const float* p = k >= ld.K0 ? b1 + (unsigned)(r * ld.ld1 + (k - ld.K0 < ld.K1 ? k - ld.K0 : 0))
                                     : b0 + (unsigned)(r * ld.ld0 + k);
-        rv[q] = *reinterpret_cast<const float4*>(p);
+        S.rv[q] = *reinterpret_cast<const float4*>(p);
       } else {
         const int kk = k < ld.K0 ? k : 0;
-        rv[q] = *reinterpret_cast<const float4*>(b0 + (unsigned)(r * ld.ld0 + kk));
+        S.rv[q] = *reinterpret_cast<const float4*>(b0 + (unsigned)(r * ld.ld0 + kk));
         if constexpr (GR) {
-          rg[q] = *reinterpret_cast<const float4*>(b1 + (unsigned)(r * ld.ld1 + kk));
-          rf[q] = brs[(unsigned)(r * rsl)];
+          S.rg[q] = *reinterpret_cast<const float4*>(b1 + (unsigned)(r * ld.ld1 + kk));
+          S.rf[q] = brs[(unsigned)(r * rsl)];
         }
       }
     }
   };
-  auto store = [&](int64_t tile, bf16* dst, float* xdst, float* udst, int t) {
+  auto store = [&](int64_t tile, int it1, int t, const Stage& S) {
+    bf16* dst = As[it1];
+    float* xdst = Xs[XIN ? it1 : 0];
+    float* udst = Us[it1];
     const int64_t row0 = tile * RT;
-    if (RS && t < RT) udst[t] = ru;
+    if (RS && t < RT) udst[t] = S.ru;
+    if constexpr (ADD) {
+      const int cpr = ep.N0 / 4;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        const int idx = t + 512 * e;
+        if (idx < RT * cpr) *reinterpret_cast<float4*>(&Is[it1][(idx / cpr) * LDO + (idx % cpr) * 4]) = S.in[e];
+      }
+    }
 #pragma unroll
     for (int q = 0; q < NA; ++q) {
       const int idx = t + 512 * q;
       const int i2 = idx % A4, rr = i2 / CPR, k = (i2 % CPR) * 4;
       const bool ok = row0 + rr < nrows && k < (AMODE == A_CAT ? ld.K0 + ld.K1 : ld.K0);
-      float4 v = rv[q];
+      float4 v = S.rv[q];
       if constexpr (XIN)
         if (idx < A4 && k < ld.K0)
           *reinterpret_cast<float4*>(&xdst[rr * LDW + k]) = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);
@@ -560,8 +597,8 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
         v.z = siluf(v.z);
         v.w = siluf(v.w);
       } else if constexpr (GR) {
-        const float4 a = rg[q];
-        const float f = ld.c * (ld.rs ? rf[q] : 1.f);
+        const float4 a = S.rg[q];
+        const float f = ld.c * (ld.rs ? S.rf[q] : 1.f);
         const float sx = sigmoidf_(a.x), sy = sigmoidf_(a.y), sz = sigmoidf_(a.z), sw = sigmoidf_(a.w);
         rd = ok ? gradsilu_part(v, a, sx, sy, sz, sw) : 0.f;
         v.x = gradsilu_scale(v.x, a.x, sx, f);
@@ -591,25 +628,20 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
 #pragma unroll
         for (int o = 1; o < 8; o <<= 1) r8 += __shfl_xor(r8, o);
         // one lane adds the row's sum; without gu the buffer is empty
-        const __amdgpu_buffer_rsrc_t G =
-            buffer_rsrc(ld.gu ? ld.gu + row0 : nullptr, ld.gu ? (nrows - row0 < RT ? nrows - row0 : RT) * 4 : 0);
-        const unsigned off = lane == 0 ? (unsigned)rr * 4 : kOutOfRange;
-        const float g0 = buf_load(G, off);
-        buf_store(g0 + ld.c * r8, G, off);
+        // (lane q holds the row's dE/du, loaded with the tile)
+        const unsigned off = lane == q ? (unsigned)rr * 4 : kOutOfRange;
+        buf_store(S.ru + ld.c * r8, gu_rsrc(row0), off);
       }
     }
   };
 
-  int64_t tile = blockIdx.x;
-  if (tile >= ntiles) return;
-  fetch(tile, tid);
-  store(tile, As[0], Xs[0], Us[0], tid);
-  // fetches are unconditional (a tile past the end is replaced by the last
-  // one, loaded and never used) so every path issues the same memory
-  // operations and the compiler's wait counts stay exact
-  fetch(tile + gridDim.x < ntiles ? tile + gridDim.x : ntiles - 1, tid);
-  __syncthreads();
-  for (int it = 0; tile < ntiles; ++it, tile += gridDim.x) {
+  const int64_t G = gridDim.x;
+  auto clampt = [&](int64_t tl) { return tl < ntiles ? tl : ntiles - 1; };
+  // One row tile: products from LDS buffer it & 1, epilogue, then the next
+  // tile's staged values into the other buffer (last read before the previous
+  // barrier) and the tile PF steps ahead into the same staging registers.
+  // Returns false after the last tile.
+  auto one = [&](int it, int64_t tile, Stage& S) -> bool {
     // The lane-dependent offsets below are loop-invariant; recomputing them
     // from an opaque copy of the thread index each iteration is cheaper than
     // the registers that hoisting them out of the loop would take.
@@ -637,71 +669,160 @@ __global__ __launch_bounds__(512) void k_gemm_ws(int NP, const bf16* __restrict_
         for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][0], acc[j], 0, 0, 0);
       }
     }
-    // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each
-    // tile; buffer stores drop rows past the end and columns past N0
-    {
-      const int64_t row0 = tile * RT;
-      const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
-      const __amdgpu_buffer_rsrc_t R0 = buffer_rsrc(ep.o0 + row0 * ep.ld0, (int64_t)nvalid * ep.ld0 * 4);
-      __amdgpu_buffer_rsrc_t R1 = R0;
-      if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD)
-        R1 = buffer_rsrc(ep.o1 + row0 * ep.ld1, (int64_t)nvalid * ep.ld1 * 4);
-      const float* lin = Xs[XIN ? it & 1 : 0];
-      float rsv[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) rsv[q] = RS ? Us[it & 1][(ln / 16) * 4 + q] : 0.f;
-#pragma unroll
-      for (int j = 0; j < NTW; ++j) {
-        const int c0 = (my0 + j) * 16;  // first column of the tile (uniform)
-        const int c = c0 + ln % 16;
-        const bool cok = j < my_nt && c < ep.N0;
-        const int cl = cok ? c : 0;  // in-range column for LDS reads
-        float in[4];
-        if constexpr (EMODE == E_ADD) {
-#pragma unroll
+    if constexpr (EPI == 0) {
+      // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each
+      // tile; buffer stores drop rows past the end and columns past N0
+      {
+        const int64_t row0 = tile * RT;
+        const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+        const __amdgpu_buffer_rsrc_t R0 = buffer_rsrc(ep.o0 + row0 * ep.ld0, (int64_t)nvalid * ep.ld0 * 4);
+        __amdgpu_buffer_rsrc_t R1 = R0;
+        if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD)
+          R1 = buffer_rsrc(ep.o1 + row0 * ep.ld1, (int64_t)nvalid * ep.ld1 * 4);
+        const float* lin = Xs[XIN ? it & 1 : 0];
+        float rsv[4];
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) rsv[q] = RS ? Us[it & 1][(ln / 16) * 4 + q] : 0.f;
+  #pragma unroll
+        for (int j = 0; j < NTW; ++j) {
+          const int c0 = (my0 + j) * 16;  // first column of the tile (uniform)
+          const int c = c0 + ln % 16;
+          const bool cok = j < my_nt && c < ep.N0;
+          const int cl = cok ? c : 0;  // in-range column for LDS reads
+          float in[4];
+          if constexpr (EMODE == E_ADD) {
+  #pragma unroll
+            for (int q = 0; q < 4; ++q) {
+              const int r = (ln / 16) * 4 + q;
+              in[q] = buf_load(R0, cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange);
+            }
+          }
+  #pragma unroll
           for (int q = 0; q < 4; ++q) {
             const int r = (ln / 16) * 4 + q;
-            in[q] = buf_load(R0, cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange);
+            const float v = acc[j][q];
+            const unsigned off0 = cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange;
+            const unsigned off1 = cok ? (unsigned)(r * ep.ld1 + c) * 4 : kOutOfRange;
+            if constexpr (EMODE == E_STORE) {
+              buf_store(v, R0, off0);
+            } else if constexpr (EMODE == E_STORE_X0) {
+              buf_store(v, R0, off0);
+              buf_store(rsv[q] * siluf(v), R1, off1);
+            } else if constexpr (EMODE == E_RESIDUAL) {
+              buf_store(v, R0, off0);
+              buf_store(residual_update(lin[r * LDW + cl], rsv[q], v), R1, off1);
+            } else if constexpr (EMODE == E_LATENT_BWD) {
+              // columns below D update g in place, the rest are the scalar adjoint
+              const bool lo = c0 < ep.D;
+              const unsigned off = !cok ? kOutOfRange : lo ? off0 : (unsigned)(r * ep.ld1 + c - ep.D) * 4;
+              buf_store(lo ? residual_adjoint(lin[r * LDW + (lo ? cl : 0)], v) : v, lo ? R0 : R1, off);
+            } else {
+              buf_store(in[q] + v, R0, off0);
+            }
           }
         }
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int r = (ln / 16) * 4 + q;
-          const float v = acc[j][q];
-          const unsigned off0 = cok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange;
-          const unsigned off1 = cok ? (unsigned)(r * ep.ld1 + c) * 4 : kOutOfRange;
+      }
+    } else {
+      // epilogue: the products go to LDS (lane holds rows 4 (ln / 16) + q,
+      // column ln % 16 of each 16x16 tile), then every thread finishes whole
+      // 16-byte chunks of rows, so the stores are contiguous row segments;
+      // buffer stores drop rows past the end
+  #pragma unroll
+      for (int j = 0; j < NTW; ++j)
+  #pragma unroll
+        for (int q = 0; q < 4; ++q) Os[((ln / 16) * 4 + q) * LDO + (my0 + j) * 16 + ln % 16] = acc[j][q];
+      __syncthreads();
+      {
+        typedef unsigned u4 __attribute__((ext_vector_type(4)));
+        const int64_t row0 = tile * RT;
+        const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+        const __amdgpu_buffer_rsrc_t R0 = buffer_rsrc(ep.o0 + row0 * ep.ld0, (int64_t)nvalid * ep.ld0 * 4);
+        __amdgpu_buffer_rsrc_t R1 = R0;
+        if constexpr (EMODE == E_STORE_X0 || EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD)
+          R1 = buffer_rsrc(ep.o1 + row0 * ep.ld1, (int64_t)nvalid * ep.ld1 * 4);
+        const float* lin = Xs[XIN ? it & 1 : 0];
+        const int cpr = ep.N0 / 4;  // chunks per output row
+  #pragma unroll
+        for (int e = 0; e < NE; ++e) {
+          const int idx = t + 512 * e;
+          const bool ok = idx < RT * cpr;
+          const int i2 = ok ? idx : 0;
+          const int r = i2 / cpr, c = (i2 % cpr) * 4;
+          const float4 v = *reinterpret_cast<const float4*>(&Os[r * LDO + c]);
+          const unsigned off0 = ok ? (unsigned)(r * ep.ld0 + c) * 4 : kOutOfRange;
+          const unsigned off1 = ok ? (unsigned)(r * ep.ld1 + c) * 4 : kOutOfRange;
+          float4 w;
           if constexpr (EMODE == E_STORE) {
-            buf_store(v, R0, off0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), R0, off0, 0, 0);
           } else if constexpr (EMODE == E_STORE_X0) {
-            buf_store(v, R0, off0);
-            buf_store(rsv[q] * siluf(v), R1, off1);
+            const float u = Us[it & 1][r];
+            w = make_float4(u * siluf(v.x), u * siluf(v.y), u * siluf(v.z), u * siluf(v.w));
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), R0, off0, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), R1, off1, 0, 0);
           } else if constexpr (EMODE == E_RESIDUAL) {
-            buf_store(v, R0, off0);
-            buf_store(residual_update(lin[r * LDW + cl], rsv[q], v), R1, off1);
+            const float u = Us[it & 1][r];
+            const float4 x = *reinterpret_cast<const float4*>(&lin[r * LDW + c]);
+            w = make_float4(residual_update(x.x, u, v.x), residual_update(x.y, u, v.y), residual_update(x.z, u, v.z),
+                            residual_update(x.w, u, v.w));
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, v), R0, off0, 0, 0);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), R1, off1, 0, 0);
           } else if constexpr (EMODE == E_LATENT_BWD) {
             // columns below D update g in place, the rest are the scalar adjoint
-            const bool lo = c0 < ep.D;
-            const unsigned off = !cok ? kOutOfRange : lo ? off0 : (unsigned)(r * ep.ld1 + c - ep.D) * 4;
-            buf_store(lo ? residual_adjoint(lin[r * LDW + (lo ? cl : 0)], v) : v, lo ? R0 : R1, off);
+            const bool lo = c < ep.D;
+            const float4 g = *reinterpret_cast<const float4*>(&lin[r * LDW + (lo ? c : 0)]);
+            w = lo ? make_float4(residual_adjoint(g.x, v.x), residual_adjoint(g.y, v.y), residual_adjoint(g.z, v.z),
+                                 residual_adjoint(g.w, v.w))
+                   : v;
+            const unsigned off = !ok ? kOutOfRange : lo ? off0 : (unsigned)(r * ep.ld1 + c - ep.D) * 4;
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), lo ? R0 : R1, off, 0, 0);
           } else {
-            buf_store(in[q] + v, R0, off0);
+            const float4 in = *reinterpret_cast<const float4*>(&Is[it & 1][r * LDO + c]);
+            w = make_float4(in.x + v.x, in.y + v.y, in.z + v.z, in.w + v.w);
+            __builtin_amdgcn_raw_buffer_store_b128(__builtin_bit_cast(u4, w), R0, off0, 0, 0);
           }
         }
       }
     }
-    // the next tile into the other buffer (last read before the previous
-    // barrier), after the epilogue so the accumulators are no longer live
-    const int64_t next = tile + gridDim.x;
-    if (next >= ntiles) break;
-    store(next, As[(it + 1) & 1], Xs[XIN ? (it + 1) & 1 : 0], Us[(it + 1) & 1], t);
-    fetch(next + gridDim.x < ntiles ? next + gridDim.x : ntiles - 1, t);
+    const int64_t next = tile + G;
+    if (next >= ntiles) return false;
+    store(next, (it + 1) & 1, t, S);
+    fetch(clampt(tile + (PF + 1) * G), t, S);
+    return true;
+  };
+
+  int64_t tile = blockIdx.x;
+  if (tile >= ntiles) return;
+  // fetches are unconditional (a tile past the end is replaced by the last
+  // one, loaded and never used) so every path issues the same memory
+  // operations and the compiler's wait counts stay exact
+  fetch(tile, tid, s0);
+  store(tile, 0, tid, s0);
+  if constexpr (PF == 1) {
+    fetch(clampt(tile + G), tid, s0);
     __syncthreads();
+    for (int it = 0;; ++it, tile += G) {
+      if (!one(it, tile, s0)) break;
+      __syncthreads();
+    }
+  } else {
+    fetch(clampt(tile + G), tid, s1);
+    fetch(clampt(tile + 2 * G), tid, s0);
+    __syncthreads();
+    for (int it = 0;; it += 2) {
+      if (!one(it, tile, s1)) break;
+      __syncthreads();
+      tile += G;
+      if (!one(it + 1, tile, s0)) break;
+      __syncthreads();
+      tile += G;
+    }
   }
 }
 
-// Weight-stationary launch of one product (gemm_ws.hip). Returns whether the
-// product's signature has a compiled kernel; launches it only when asked.
-bool gemm_ws(bool launch, int kind, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt, const int* nrows,
-             const ALoad& ld, const Epi& ep);
+// Weight-stationary launch of one product (gemm_ws.hip) with epilogue form 0
+// or 1. Returns whether the product's signature has a compiled kernel;
+// launches it only when asked.
+bool gemm_ws(bool launch, int form, int kind, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt,
+             const int* nrows, const ALoad& ld, const Epi& ep);
 
 }  // namespace nq

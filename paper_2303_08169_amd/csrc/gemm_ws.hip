@@ -11,17 +11,20 @@ namespace nq {
 
 namespace {
 
-// (K steps, 16-column tiles per wavefront, A loader, epilogue)
+// (K steps, 16-column tiles per wavefront, A loader, epilogue, row tiles in
+// flight beyond the current one; 1 where the weights leave no room for two).
+// Each signature has two epilogue forms (per-lane stores, or whole rows
+// through LDS); the autotuner picks one per product.
 #define NQ_WS_LIST(X)                     \
-  X(11, 2, A_CAT, E_RESIDUAL)             \
-  X(8, 3, A_GRADSILU, E_LATENT_BWD)       \
-  X(4, 2, A_SILU, E_STORE_X0)             \
-  X(6, 2, A_PLAIN, E_ADD)                 \
-  X(3, 2, A_PLAIN, E_ADD)                 \
-  X(8, 1, A_GRADSILU, E_STORE)            \
-  X(4, 2, A_GRADSILU, E_STORE)            \
-  X(8, 2, A_PLAIN, E_STORE)               \
-  X(8, 1, A_PLAIN, E_STORE)
+  X(11, 2, A_CAT, E_RESIDUAL, 2)          \
+  X(8, 3, A_GRADSILU, E_LATENT_BWD, 1)    \
+  X(4, 2, A_SILU, E_STORE_X0, 2)          \
+  X(6, 2, A_PLAIN, E_ADD, 2)              \
+  X(3, 2, A_PLAIN, E_ADD, 2)              \
+  X(8, 1, A_GRADSILU, E_STORE, 2)         \
+  X(4, 2, A_GRADSILU, E_STORE, 2)         \
+  X(8, 2, A_PLAIN, E_STORE, 2)            \
+  X(8, 1, A_PLAIN, E_STORE, 2)
 
 // Workgroups resident at once (occupancy query x CUs), cached per kernel.
 template <class K>
@@ -40,15 +43,15 @@ unsigned resident(K kernel, int num_cu) {
 }
 
 template <int KIND>
-bool ws_dispatch(bool launch, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt, const int* nrows,
+bool ws_dispatch(bool launch, int form, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt, const int* nrows,
                  const ALoad& ld, const Epi& ep) {
-  if (Kp % 32 != 0 || NP % 16 != 0) return false;
+  if (Kp % 32 != 0 || NP % 16 != 0 || ep.N0 % 4 != 0) return false;
   if (ld.gu && Kp != 256) return false;  // one wavefront's load must cover one row
   const int KS = Kp / 32, NTW = (NP / 16 + 7) / 8;
-#define NQ_WS_CASE(ks, ntw, am, em)                                                                        \
+#define NQ_WS_CASE(ks, ntw, am, em, pf)                                                                    \
   if (KS == ks && NTW == ntw && ld.mode == am && ep.mode == em) {                                          \
     if (launch) {                                                                                          \
-      auto kern = k_gemm_ws<KIND, ntw, ks, am, em>;                                                        \
+      auto kern = form == 0 ? k_gemm_ws<KIND, ntw, ks, am, em, pf, 0> : k_gemm_ws<KIND, ntw, ks, am, em, pf, 1>; \
       kern<<<resident(kern, num_cu), 512, 0, s>>>(NP, static_cast<const bf16*>(Bt), nrows, ld, ep);         \
     }                                                                                                      \
     return true;                                                                                           \
@@ -60,10 +63,10 @@ bool ws_dispatch(bool launch, hipStream_t s, int num_cu, int NP, int Kp, const v
 
 }  // namespace
 
-bool gemm_ws(bool launch, int kind, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt, const int* nrows,
-             const ALoad& ld, const Epi& ep) {
-  if (kind == G_BF16X3) return ws_dispatch<G_BF16X3>(launch, s, num_cu, NP, Kp, Bt, nrows, ld, ep);
-  if (kind == G_BF16) return ws_dispatch<G_BF16>(launch, s, num_cu, NP, Kp, Bt, nrows, ld, ep);
+bool gemm_ws(bool launch, int form, int kind, hipStream_t s, int num_cu, int NP, int Kp, const void* Bt,
+             const int* nrows, const ALoad& ld, const Epi& ep) {
+  if (kind == G_BF16X3) return ws_dispatch<G_BF16X3>(launch, form, s, num_cu, NP, Kp, Bt, nrows, ld, ep);
+  if (kind == G_BF16) return ws_dispatch<G_BF16>(launch, form, s, num_cu, NP, Kp, Bt, nrows, ld, ep);
   return false;
 }
 

@@ -1092,8 +1092,8 @@ double gemm_bytes_per_row(const ALoad& ld, const Epi& ep) {
 
 // y = A W (fwd) or gA = gy W^T (bwd) for one stored linear map. The kernel is
 // the model's tuned choice for this product (or the one being timed): one of
-// the tile shapes of k_gemm or, where compiled, the weight-stationary k_gemm_ws
-// (the last variant).
+// the tile shapes of k_gemm or, where compiled, the two epilogue forms of the
+// weight-stationary k_gemm_ws (the last two variants).
 void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& ld, const Epi& ep,
           const std::string& name) {
   const Workspace& ws = ctx->ws;
@@ -1115,13 +1115,16 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
                    : (m->dims.prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32);
   const void* Bbf = (bwd ? L.bf_bwd : L.bf_fwd).p;
   const int ntile = gemm_variants(kind, NP);
-  const bool has_ws = gemm_ws(false, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
-  const int nv = ntile + (has_ws ? 1 : 0);
+  const bool has_ws = gemm_ws(false, 0, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
+  const int nv = ntile + (has_ws ? 2 : 0);
   ctx->site_np[name] = NP;
   ctx->site_nvar[name] = nv;
-  v = ctx->force_variant < 0 && ctx->user_variant == NQ_VARIANT_LAST ? nv - 1 : v % nv;
-  if (has_ws && v == ntile) {
-    gemm_ws(true, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
+  if (ctx->force_variant < 0 && ctx->user_variant <= NQ_VARIANT_LAST)
+    v = std::max(0, nv + 1 + ctx->user_variant);  // LAST: nv - 1, LAST2: nv - 2
+  else
+    v %= nv;
+  if (has_ws && v >= ntile) {
+    gemm_ws(true, v - ntile, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
     NQ_HIP(hipGetLastError());
     span_end(ctx, sp);
     return;

@@ -183,9 +183,10 @@ class Potential:
         return json.loads(buf.value.decode())
 
     def set_variant(self, variant: int):
-        """Kernel choice of the matrix-core products: -1 tuned (default), -2 the
-        last variant of each product (weight-stationary where compiled), v >= 0
-        variant v of each. Results are bitwise identical for every choice."""
+        """Kernel choice of the matrix-core products: -1 tuned (default), -2 / -3
+        the last / second-to-last variant of each product (the two epilogue forms
+        of the weight-stationary kernel where compiled), v >= 0 variant v of
+        each. Results are bitwise identical for every choice."""
         B.check(self.lib.nq_ctx_set_variant(self._ctx, int(variant)), self._ctx)
 
     def set_workspace_budget(self, nbytes: int):

@@ -81,14 +81,15 @@ def test_autotune_keeps_results_bitwise():
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 def test_kernel_variants_bitwise(prec):
     """Every kernel choice of the matrix-core products (tile shapes of the
-    tiled kernel, the weight-stationary kernel) gives the same bits. (The
+    tiled kernel, both epilogue forms of the weight-stationary kernel) gives
+    the same bits. (The
     27,648-atom test repeats this at a ragged edge count: 2,372,786 rows.)"""
     from paper_2303_08169_amd.potential import Potential
     cf, pos, z, L, w = system("nh3_1024_l2")
     pot = Potential(cf.model, w, prec)
     P, Z = _dev(pos, z)
     ref = None
-    for v in (0, 1, -2):
+    for v in (0, 1, -2, -3):
         pot.set_variant(v)
         E, F, Ei = pot.energy_forces(P, Z, L, atom_energy=True)
         torch.cuda.synchronize()
@@ -100,5 +101,5 @@ def test_kernel_variants_bitwise(prec):
             assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
     from paper_2303_08169_amd.binding import NQError
     with pytest.raises(NQError):
-        pot.set_variant(-3)
+        pot.set_variant(-4)
     pot.close()

@@ -158,12 +158,13 @@ def test_full_size_sampled_bf16x3():
     assert abs(E.item() - Ei.sum()) <= 1e-9 * np.abs(Ei).sum()
     np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-6 * np.abs(F).sum())
     assert abs(ne / len(pos) - cf.model.avg_num_neighbors) < 0.05 * cf.model.avg_num_neighbors
-    # the weight-stationary products (last variant) give the same bits
-    pot.set_variant(-2)
-    E2, F2 = pot.energy_forces(P, Z, L)
-    torch.cuda.synchronize()
-    assert E2.item() == E.item()
-    assert np.array_equal(F2.cpu().numpy(), F)
+    # both forms of the weight-stationary products give the same bits
+    for v in (-2, -3):
+        pot.set_variant(v)
+        E2, F2 = pot.energy_forces(P, Z, L)
+        torch.cuda.synchronize()
+        assert E2.item() == E.item()
+        assert np.array_equal(F2.cpu().numpy(), F)
     pot.close()
 
 
