@@ -253,22 +253,29 @@ template <int LMAX> struct TPSize {
   static constexpr int NT = LMAX == 1 ? 8 : 35;  // sum over paths of (2 l3 + 1)
 };
 
-// Loads V_{t-1}[lm] of edge e, channel c (t = 1: w0[l][c] * Y[lm]).
-template <int NY>
+// Raw loads of V_{t-1} for one (edge, channel), with no arithmetic on the
+// loaded values, so the loads of a prefetched group stay in flight until the
+// group is processed. First layer: V0[lm] = w0[l] Y[lm] is formed at use
+// (vprev_value) from R = Y and W = w0; later layers: R = V_{t-1} (W reads R's
+// row and is unused). One 64-bit row address per source, components at fixed
+// offsets from it; the uniform selects keep the loads branch-free.
+template <int NY, int NL>
 __device__ inline void load_vprev(bool first, int64_t e, int c, int C, const float* we1, int ldwe,
-                                  const float* vprev, const float* Y, float* V) {
-  // one 64-bit row address per source; the components are fixed offsets from it
-  const float* w = we1 + e * ldwe + c;
+                                  const float* vprev, const float* Y, float (&R)[NY], float (&W)[NL]) {
   const float* v = vprev + e * (NY * C) + c;
+  const float* rb = first ? Y : v;
+  const int rs = first ? 1 : C;
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) {
-    if (first) {
-      const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
-      V[lm] = w[l * C] * Y[lm];
-    } else {
-      V[lm] = v[lm * C];
-    }
-  }
+  for (int lm = 0; lm < NY; ++lm) R[lm] = rb[lm * rs];
+  const float* wb = first ? we1 + e * ldwe + c : v;
+  const int ws = first ? C : 0;
+#pragma unroll
+  for (int l = 0; l < NL; ++l) W[l] = wb[l * ws];
+}
+template <int NY, int NL>
+__device__ inline float vprev_value(bool first, const float (&R)[NY], const float (&W)[NL], int lm) {
+  const int l = lm >= 4 ? 2 : (lm >= 1 ? 1 : 0);
+  return first ? W[l] * R[lm] : R[lm];
 }
 
 // Coupling paths of one l3 group: count, offsets of their components in the
@@ -485,18 +492,21 @@ struct TpFwdArgs {
   float* vout;
 };
 
-// Inputs of the forward product of one (edge, channel): V_{t-1} and Gamma_i.
+// Inputs of the forward product of one (edge, channel): V_{t-1} (raw, see
+// load_vprev) and Gamma_i.
 template <int LMAX> struct TpFwdIn {
   static constexpr int NY = TPSize<LMAX>::NY;
-  float V[NY], G[NY];
+  float V[NY], W[LMAX + 1], G[NY];
 };
 
+// ctr: the edge's centre (its index load issued a group earlier, so the Gamma
+// loads do not wait on it).
 template <int LMAX, int CC>
-__device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int c, TpFwdIn<LMAX>& in) {
+__device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int ctr, int c, TpFwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = CC > 0 ? CC : a.C;
-  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
-  const float* g = a.gam + (int64_t)a.ei[e] * (NY * C) + c;
+  load_vprev(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V, in.W);
+  const float* g = a.gam + (int64_t)ctr * (NY * C) + c;
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) in.G[lm] = g[lm * C];
 }
@@ -510,6 +520,10 @@ template <int LMAX, int CC>
 __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, int c, float* Trow, int CP,
                                    const TpFwdIn<LMAX>& in) {
   const int C = CC > 0 ? CC : a.C;
+  constexpr int NY = TPSize<LMAX>::NY;
+  float V[NY];
+#pragma unroll
+  for (int lm = 0; lm < NY; ++lm) V[lm] = vprev_value(a.first, in.V, in.W, lm);
   float* srow = a.s + e * a.lds + c;
   for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
@@ -520,7 +534,7 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, in
 #pragma unroll
         for (int m2 = 0; m2 < 2 * l2 + 1; ++m2) {
           const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
-          if (cgv != 0.f) acc += cgv * in.V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
+          if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
       Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;
       if (l3 == 0 && valid) srow[qs * C] = acc;
@@ -550,18 +564,27 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   // Software pipeline over the workgroup's groups: the next group's inputs are
   // loaded while this group is mixed. A row past the last edge reads the last
   // edge and contributes zeros.
-  auto issue = [&](int64_t g, TpFwdIn<LMAX>& inr) {
+  // The centre index of a group is loaded one group earlier still.
+  auto edge_of = [&](int64_t g) {
     const int64_t eg = g * epb + el;
-    tp_fwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, eg < ne ? eg : ne - 1, c, inr);
+    return eg < ne ? eg : ne - 1;
+  };
+  auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
+  auto issue = [&](int64_t g, int ctr, TpFwdIn<LMAX>& inr) {
+    tp_fwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, edge_of(g), ctr, c, inr);
   };
   TpFwdIn<LMAX> in;
   int64_t grp = blockIdx.x;
-  if (grp < ngroups) issue(grp, in);
+  int ctr = 0;
+  if (grp < ngroups) {
+    issue(grp, a.ei[edge_of(grp)], in);
+    ctr = a.ei[edge_of(clampg(grp + gridDim.x))];
+  }
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     tp_fwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, e < ne, c, Tl + el * NT * CP, CP, in);
-    const int64_t nx = grp + gridDim.x;
-    issue(nx < ngroups ? nx : grp, in);
+    issue(clampg(grp + gridDim.x), ctr, in);
+    ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     if (a.last) continue;
     __syncthreads();
     if constexpr (MW >= 0)
@@ -679,15 +702,16 @@ struct TpBwdArgs {
 // group's mixing so that their HBM latency overlaps it.
 template <int LMAX> struct TpBwdIn {
   static constexpr int NY = TPSize<LMAX>::NY, NS = LMAX + 1;  // scalar paths: (l, l, 0)
-  float V[NY], G[NY], gs[NS];
+  float V[NY], W[LMAX + 1], G[NY], gs[NS];
 };
 
+// ctr as in tp_fwd_load.
 template <int LMAX, int CC>
-__device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int c, TpBwdIn<LMAX>& in) {
+__device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int ctr, int c, TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = CC > 0 ? CC : a.C;
-  load_vprev<NY>(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V);
-  const float* g = a.gam + (int64_t)a.ei[e] * (NY * C) + c;
+  load_vprev(a.first, e, c, C, a.we1, a.ldwe, a.vprev, a.geo + e * kGeo + kGeoY, in.V, in.W);
+  const float* g = a.gam + (int64_t)ctr * (NY * C) + c;
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) in.G[lm] = g[lm * C];
   const float* gsr = a.gs + e * a.ldgs + c;
@@ -699,17 +723,21 @@ __device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int c, TpBwdIn
 // mixing adjoint (gTrow: this edge's rows in LDS, unused for the last layer)
 // and dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i,
 // and either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
-// the w0 part of dE/dY into gY. CC: channel count if known at compile time.
+// the w0 part of dE/dY into gvout (16 per edge; a plain store, which the
+// geometry adjoint adds to gY: a read-modify-write here would wait on every
+// outstanding load of the next group). CC: channel count if known at compile
+// time.
 template <int LMAX, int CC>
 __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP,
                                    const TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = CC > 0 ? CC : a.C;
-  float gV[NY], gG[NY];
+  float gV[NY], gG[NY], V[NY];
 #pragma unroll
   for (int k = 0; k < NY; ++k) {
     gV[k] = 0.f;
     gG[k] = 0.f;
+    V[k] = vprev_value(a.first, in.V, in.W, k);
   }
   for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
@@ -724,7 +752,7 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
           if (cgv != 0.f) {
             const float w = cgv * g;
             gV[l1 * l1 + m1] += w * in.G[l2 * l2 + m2];
-            gG[l2 * l2 + m2] += w * in.V[l1 * l1 + m1];
+            gG[l2 * l2 + m2] += w * V[l1 * l1 + m1];
           }
         }
     }
@@ -740,20 +768,19 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
     // V0[c][lm] = w0[l][c] Y[lm]. The channel sums for dE/dY reduce each
     // component right away: gathering all of them first for add_group_sums
     // raises the register peak of the 32-channel kernel into spills.
-    const float* Y = a.geo + e * kGeo + kGeoY;
-    const float* w0r = a.we1 + e * a.ldwe + c;
+    // (the first layer's raw inputs: in.V holds Y, in.W holds w0)
     float* gwr = a.gew + e * a.ldgew + c;
-    float* gYr = a.gY + e * 16;
+    float* gYr = a.gvout + e * 16;
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       float gw = 0.f;
-      const float w0 = w0r[l * C];
+      const float w0 = in.W[l];
 #pragma unroll
       for (int m = 0; m < 2 * l + 1; ++m) {
-        gw += gV[l * l + m] * Y[l * l + m];
+        gw += gV[l * l + m] * in.V[l * l + m];
         float part = w0 * gV[l * l + m];
         for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-        if (c == 0) gYr[l * l + m] += part;
+        if (c == 0) gYr[l * l + m] = part;
       }
       gwr[l * C] = gw;
     }
@@ -783,18 +810,27 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   // last edge reads the last edge.
   float gv[NY];
   TpBwdIn<LMAX> in;
-  auto issue = [&](int64_t g, float (&gvr)[NY], TpBwdIn<LMAX>& inr) {
+  // The centre index of a group is loaded one group earlier still.
+  auto edge_of = [&](int64_t g) {
     const int64_t eg = g * epb + el;
-    const int64_t ec = eg < ne ? eg : ne - 1;
+    return eg < ne ? eg : ne - 1;
+  };
+  auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
+  auto issue = [&](int64_t g, int ctr, float (&gvr)[NY], TpBwdIn<LMAX>& inr) {
+    const int64_t ec = edge_of(g);
     if (!a.last) {
       const float* src = a.gvin + ec * (NY * C) + c;
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) gvr[lm] = src[lm * C];
     }
-    tp_bwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, ec, c, inr);
+    tp_bwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, ec, ctr, c, inr);
   };
   int64_t grp = blockIdx.x;
-  if (grp < ngroups) issue(grp, gv, in);
+  int ctr = 0;
+  if (grp < ngroups) {
+    issue(grp, a.ei[edge_of(grp)], gv, in);
+    ctr = a.ei[edge_of(clampg(grp + gridDim.x))];
+  }
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
@@ -812,8 +848,8 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     }
     float gvn[NY];
     TpBwdIn<LMAX> inn;
-    const int64_t nx = grp + gridDim.x;
-    issue(nx < ngroups ? nx : grp, gvn, inn);
+    issue(clampg(grp + gridDim.x), ctr, gvn, inn);
+    ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     if (valid) tp_bwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, c, gTl + el * NT * CP, CP, in);
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
@@ -911,9 +947,11 @@ __device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, 
   gz = s3 * gY[3] + s15 * (y * gY[5] + x * gY[7]) + 3.f * s5 * z * gY[6];
 }
 
-// Adjoint of the edge geometry: dE/dr_ij from dE/du, dE/dY and dE/db.
+// Adjoint of the edge geometry: dE/dr_ij from dE/du, dE/dY (the environment
+// sums' part gYb plus the first tensor product's part gYt) and dE/db.
 __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __restrict__ geo,
                                const float* __restrict__ gu, const float* __restrict__ gYb,
+                               const float* __restrict__ gYt,
                                const float* __restrict__ gh0, int ldh0, int boff, int nb, int p, float rc, int NY,
                                const int* __restrict__ e0p, float4* __restrict__ gr) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -941,7 +979,7 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
   gd += gut * dudx / rc;
   float gY[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) gY[k] = (k < NY) ? gYb[e * 16 + k] : 0.f;
+  for (int k = 0; k < 9; ++k) gY[k] = (k < NY) ? gYb[e * 16 + k] + gYt[e * 16 + k] : 0.f;
   float ax, ay, az;
   sph_grad_dot(gY, x, y, z, ax, ay, az);
   const float rad = ax * x + ay * y + az * z;
@@ -1244,9 +1282,9 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const size_t lds = tp_lds_bytes(d.C, d.L, true);
   // bytes per edge: dE/dV_t, V_{t-1} (w0 and Y for t = 1), the centre index,
   // dE/ds, the dE/dGamma contributions, and dE/dV_{t-1} (t > 1) or dE/dw0
-  // plus the read-modify-write of dE/dY (t = 1); per atom: Gamma read once
+  // plus the w0 part of dE/dY (t = 1); per atom: Gamma read once
   const double vin = t == 1 ? 4.0 * (d.NW + d.NY) : 4.0 * d.NY * d.C;
-  const double vout = t == 1 ? 4.0 * d.NW + 8.0 * d.NY : 4.0 * d.NY * d.C;
+  const double vout = t == 1 ? 4.0 * d.NW + 4.0 * d.NY : 4.0 * d.NY * d.C;
   const double bpe = (last ? 0.0 : 4.0 * d.NY * d.C) + vin + 4.0 + 4.0 * d.nscal * d.C + 4.0 * d.NY * d.C + vout;
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1], bpe, 0,
                             4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
@@ -1589,6 +1627,7 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     }
   }
   int gvcur = 0;  // ws.gv[gvcur] holds dE/dV_t while processing layer t (t < T)
+  const float* gYt = nullptr;
   for (int t = d.T; t >= 1; --t) {
     const int kl = d.n_lat - 1;
     float* gout = nullptr;
@@ -1606,6 +1645,7 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
       gout = ws.gh[k % 2];
     }
     // tensor-product adjoint, then the environment-sum adjoint -> gew[:, NW:2NW], gY
+    if (t == 1) gYt = ws.gv[1 - gvcur];  // receives the first product's part of dE/dY
     launch_tp_bwd(ctx, m, t, ws.gv[gvcur], ws.gv[1 - gvcur]);
     gvcur = 1 - gvcur;
     launch_env_bwd(ctx, m, t);
@@ -1628,9 +1668,9 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     gout = ws.gh[k % 2];
   }
   {
-    // per edge: geo row, gu, dE/dY, dE/db, the edge slot, g_ij written
-    const int sp_ = span_begin(ctx, "geometry_bwd", 0, 4.0 * kGeo + 4.0 + 4.0 * d.NY + 4.0 * d.nb + 4.0 + 16.0);
-    k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gout, ws.maxw, 2 * d.S, d.nb,
+    // per edge: geo row, gu, dE/dY (two parts), dE/db, the edge slot, g_ij written
+    const int sp_ = span_begin(ctx, "geometry_bwd", 0, 4.0 * kGeo + 4.0 + 8.0 * d.NY + 4.0 * d.nb + 4.0 + 16.0);
+    k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gYt, gout, ws.maxw, 2 * d.S, d.nb,
                                                             d.p, (float)d.rc, d.NY, ws.v_e0, ws.gr);
     span_end(ctx, sp_);
   }
