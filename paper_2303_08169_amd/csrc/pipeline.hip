@@ -695,6 +695,7 @@ struct TpBwdArgs {
   float* gew;
   int ldgew;
   float* gY;
+  int ldgy;
 };
 
 // Inputs of the adjoint of one (edge, channel) that do not depend on the
@@ -723,10 +724,10 @@ __device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int ctr, int c
 // mixing adjoint (gTrow: this edge's rows in LDS, unused for the last layer)
 // and dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i,
 // and either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
-// the w0 part of dE/dY into gvout (16 per edge; a plain store, which the
-// geometry adjoint adds to gY: a read-modify-write here would wait on every
-// outstanding load of the next group). CC: channel count if known at compile
-// time.
+// the w0 part of dE/dY into slot 0 of the edge's dE/dY row (a plain store:
+// the geometry adjoint adds the slots, and a read-modify-write here would wait
+// on every outstanding load of the next group). CC: channel count if known at
+// compile time.
 template <int LMAX, int CC>
 __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP,
                                    const TpBwdIn<LMAX>& in) {
@@ -770,7 +771,7 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
     // raises the register peak of the 32-channel kernel into spills.
     // (the first layer's raw inputs: in.V holds Y, in.W holds w0)
     float* gwr = a.gew + e * a.ldgew + c;
-    float* gYr = a.gvout + e * 16;
+    float* gYr = a.gY + e * a.ldgy;
 #pragma unroll
     for (int l = 0; l <= LMAX; ++l) {
       float gw = 0.f;
@@ -877,15 +878,18 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // centre per wavefront (lanes: channel c, group g of G = 64 / C):
 //   dGamma_i[lm][c] = nu^-1/2 sum_k ggc[k][lm][c]      (groups split the edges)
 //   de_k[l][c]      = sum_m dGamma_i[lm][c] Y_k[lm]     -> gew[:, gcol + l*C + c]
-//   dY_k[lm]       += sum_c e_k[l][c] dGamma_i[lm][c]   (channel sums spread over lanes)
+//   dY_k[lm]        = sum_c e_k[l][c] dGamma_i[lm][c]   (channel sums spread over lanes)
 // dGamma_i stays in registers between the two passes over the centre's edges.
+// dY_k goes to this layer's own 16-float slot of the edge's dE/dY row (plain
+// stores; the geometry adjoint adds the slots), and the second pass loads the
+// next edge's inputs before working on the current one.
 template <int NY, int C>
 __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __restrict__ nedge_p,
                                                      const int* __restrict__ eoff, const float* __restrict__ ggc,
                                                      const float* __restrict__ esrc, int lde,
                                                      const float* __restrict__ geo, float scale,
                                                      float* __restrict__ gew, int ldgew, int gcol,
-                                                     float* __restrict__ gY) {
+                                                     float* __restrict__ gY, int ldgy) {
   constexpr int G = 64 / C, L = NY == 9 ? 2 : (NY == 4 ? 1 : 0);
   const int64_t i = (int64_t)blockIdx.x * 4 + threadIdx.x / 64;
   if (i >= n) return;
@@ -897,17 +901,16 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) dg[lm] = 0.f;
   int k = b + g;
-  for (; k + G < e1; k += 2 * G) {  // two edges per group in flight
-    float v0[NY], v1[NY];
+  for (; k + 3 * G < e1; k += 4 * G) {  // four edges per group in flight
+    float v[4][NY];
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) {
-      v0[lm] = ggc[((int64_t)k * NY + lm) * C + c];
-      v1[lm] = ggc[((int64_t)(k + G) * NY + lm) * C + c];
-    }
+    for (int u = 0; u < 4; ++u)
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) dg[lm] += v0[lm] + v1[lm];
+      for (int lm = 0; lm < NY; ++lm) v[u][lm] = ggc[((int64_t)(k + u * G) * NY + lm) * C + c];
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) dg[lm] += (v[0][lm] + v[1][lm]) + (v[2][lm] + v[3][lm]);
   }
-  if (k < e1) {
+  for (; k < e1; k += G) {
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) dg[lm] += ggc[((int64_t)k * NY + lm) * C + c];
   }
@@ -917,11 +920,24 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
     for (int lm = 0; lm < NY; ++lm) dg[lm] += __shfl_xor(dg[lm], o);
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) dg[lm] *= scale;
-  for (int kk = b + g; kk < e1; kk += G) {
-    const float* Y = geo + (int64_t)kk * kGeo + kGeoY;
-    float ev[L + 1], prod[NY];
+  // inputs of edge kk2 (a row past the centre's last edge reads the last one)
+  auto load = [&](int kk2, float (&Yv)[NY], float (&evv)[L + 1]) {
+    const int kc = kk2 < e1 ? kk2 : e1 - 1;
+    const float* Yr = geo + (int64_t)kc * kGeo + kGeoY;
 #pragma unroll
-    for (int l = 0; l <= L; ++l) ev[l] = esrc[(int64_t)kk * lde + l * C + c];
+    for (int lm = 0; lm < NY; ++lm) Yv[lm] = Yr[lm];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) evv[l] = esrc[(int64_t)kc * lde + l * C + c];
+  };
+  float Yn[NY], evn[L + 1];
+  if (b + g < e1) load(b + g, Yn, evn);
+  for (int kk = b + g; kk < e1; kk += G) {
+    float Y[NY], ev[L + 1], prod[NY];
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) Y[lm] = Yn[lm];
+#pragma unroll
+    for (int l = 0; l <= L; ++l) ev[l] = evn[l];
+    load(kk + G, Yn, evn);
 #pragma unroll
     for (int l = 0; l <= L; ++l) {
       float ge = 0.f;
@@ -936,7 +952,7 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
     spread_sum<NY, C>(prod, c, first, count);
 #pragma unroll
     for (int q = 0; q < NY; ++q)
-      if (q < count) gY[(int64_t)kk * 16 + first + q] += prod[q];
+      if (q < count) gY[(int64_t)kk * ldgy + first + q] = prod[q];
   }
 }
 
@@ -947,11 +963,11 @@ __device__ inline void sph_grad_dot(const float* gY, float x, float y, float z, 
   gz = s3 * gY[3] + s15 * (y * gY[5] + x * gY[7]) + 3.f * s5 * z * gY[6];
 }
 
-// Adjoint of the edge geometry: dE/dr_ij from dE/du, dE/dY (the environment
-// sums' part gYb plus the first tensor product's part gYt) and dE/db.
+// Adjoint of the edge geometry: dE/dr_ij from dE/du, dE/dY (the sum of the
+// nslot 16-float slots of the edge's row in gYb: the first tensor product's
+// part, then each layer's environment-sum part) and dE/db.
 __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __restrict__ geo,
-                               const float* __restrict__ gu, const float* __restrict__ gYb,
-                               const float* __restrict__ gYt,
+                               const float* __restrict__ gu, const float* __restrict__ gYb, int nslot,
                                const float* __restrict__ gh0, int ldh0, int boff, int nb, int p, float rc, int NY,
                                const int* __restrict__ e0p, float4* __restrict__ gr) {
   const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -979,7 +995,24 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
   gd += gut * dudx / rc;
   float gY[9];
 #pragma unroll
-  for (int k = 0; k < 9; ++k) gY[k] = (k < NY) ? gYb[e * 16 + k] + gYt[e * 16 + k] : 0.f;
+  for (int k = 0; k < 9; ++k) gY[k] = 0.f;
+  // slots in order, each as three 16-byte loads (components 0..11), all issued
+  // before the sums (at most 5 slots: T <= 4)
+  float4 q[5][3];
+  const float4* row = reinterpret_cast<const float4*>(gYb + e * nslot * 16);
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) q[r][j] = r < nslot ? row[r * 4 + j] : make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+  for (int r = 0; r < 5; ++r)
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+      const float w[4] = {q[r][j].x, q[r][j].y, q[r][j].z, q[r][j].w};
+#pragma unroll
+      for (int u = 0; u < 4; ++u)
+        if (j * 4 + u < 9 && j * 4 + u < NY) gY[j * 4 + u] += w[u];
+    }
   float ax, ay, az;
   sph_grad_dot(gY, x, y, z, ax, ay, az);
   const float rad = ax * x + ay * y + az * z;
@@ -1278,7 +1311,7 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const bool last = t == d.T;
   const TpBwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
                     ws.gs, d.nscal * d.C, last ? nullptr : gvin, layer_mix(m, t), ws.ggc, gvout, ws.gew,
-                    2 * d.NW, ws.gY};
+                    2 * d.NW, ws.gY, 16 * (d.T + 1)};
   const size_t lds = tp_lds_bytes(d.C, d.L, true);
   // bytes per edge: dE/dV_t, V_{t-1} (w0 and Y for t = 1), the centre index,
   // dE/ds, the dE/dGamma contributions, and dE/dV_{t-1} (t > 1) or dE/dw0
@@ -1315,12 +1348,13 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
   const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
   const int lde = t == 1 ? 2 * d.NW : d.NW;
   const float scale = (float)d.inv_sqrt_nu;
-  // per edge: the dE/dGamma contributions, e, Y, dE/de written, dE/dY read-modify-write
+  // per edge: the dE/dGamma contributions, e, Y, dE/de and dE/dY written
   const int sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0,
-                            4.0 * d.NY * d.C + 8.0 * d.NW + 4.0 * d.NY + 8.0 * d.NY, 0, 4.0);
+                            4.0 * d.NY * d.C + 8.0 * d.NW + 4.0 * d.NY + 4.0 * d.NY, 0, 4.0);
 #define NQ_ENVB(NYV, CV)                                                                                   \
   k_env_adjoint<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, esrc, lde, \
-                                                                  ws.geo, scale, ws.gew, 2 * d.NW, d.NW, ws.gY)
+                                                                  ws.geo, scale, ws.gew, 2 * d.NW, d.NW,       \
+                                                                  ws.gY + 16 * t, 16 * (d.T + 1))
   NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVB);
 #undef NQ_ENVB
   NQ_HIP(hipGetLastError());
@@ -1470,7 +1504,7 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
   ws.gv[1] = fbuf(cap, d.NY * d.C);
   ws.ggc = fbuf(cap, d.NY * d.C);
   ws.gew = fbuf(cap, 2 * d.NW);
-  ws.gY = fbuf(cap, 16);
+  ws.gY = fbuf(cap, 16 * (d.T + 1));  // dE/dY: one 16-float slot per contributor
   ws.gu = fbuf(cap, 1);
   ws.gr = ws.grbuf.as<float4>();
 }
@@ -1607,11 +1641,6 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     k_fill<<<grid_for(cap, 256), 256, 0, s>>>(ws.gu, cap, 0.f);
     span_end(ctx, sp_);
   }
-  {
-    const int sp_ = span_begin(ctx, "fill");
-    k_fill<<<grid_for(cap * 16, 256), 256, 0, s>>>(ws.gY, cap * 16, 0.f);
-    span_end(ctx, sp_);
-  }
   // edge MLP: g_a(last) = sigma_E w_out SiLU'(a)
   {
     float* gout = nullptr;
@@ -1627,7 +1656,6 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     }
   }
   int gvcur = 0;  // ws.gv[gvcur] holds dE/dV_t while processing layer t (t < T)
-  const float* gYt = nullptr;
   for (int t = d.T; t >= 1; --t) {
     const int kl = d.n_lat - 1;
     float* gout = nullptr;
@@ -1645,7 +1673,6 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
       gout = ws.gh[k % 2];
     }
     // tensor-product adjoint, then the environment-sum adjoint -> gew[:, NW:2NW], gY
-    if (t == 1) gYt = ws.gv[1 - gvcur];  // receives the first product's part of dE/dY
     launch_tp_bwd(ctx, m, t, ws.gv[gvcur], ws.gv[1 - gvcur]);
     gvcur = 1 - gvcur;
     launch_env_bwd(ctx, m, t);
@@ -1668,9 +1695,10 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
     gout = ws.gh[k % 2];
   }
   {
-    // per edge: geo row, gu, dE/dY (two parts), dE/db, the edge slot, g_ij written
-    const int sp_ = span_begin(ctx, "geometry_bwd", 0, 4.0 * kGeo + 4.0 + 8.0 * d.NY + 4.0 * d.nb + 4.0 + 16.0);
-    k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, gYt, gout, ws.maxw, 2 * d.S, d.nb,
+    // per edge: geo row, gu, dE/dY (T + 1 parts), dE/db, the edge slot, g_ij written
+    const int sp_ = span_begin(ctx, "geometry_bwd", 0,
+                               4.0 * kGeo + 4.0 + 4.0 * (d.T + 1) * d.NY + 4.0 * d.nb + 4.0 + 16.0);
+    k_geometry_bwd<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.geo, ws.gu, ws.gY, d.T + 1, gout, ws.maxw, 2 * d.S, d.nb,
                                                             d.p, (float)d.rc, d.NY, ws.v_e0, ws.gr);
     span_end(ctx, sp_);
   }
