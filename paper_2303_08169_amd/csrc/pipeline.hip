@@ -207,6 +207,22 @@ __device__ inline void spread_sum(float (&v)[N], int lane, int& first, int& coun
   count = len > 0 ? len : 0;
 }
 
+// Sum of v over each aligned group of 32 lanes with DPP lane moves (no LDS
+// round trips): pair, quad, half-row mirror, row mirror, then row 1 (3) adds
+// row 0's (2's) lane 15. The total is valid in lanes 16..31 and 48..63.
+template <int CTRL, int ROWS>
+__device__ inline float dpp_mov(float x) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, x), CTRL, ROWS, 0xF, false));
+}
+__device__ inline float sum32_dpp(float v) {
+  v += dpp_mov<0xB1, 0xF>(v);   // quad_perm [1, 0, 3, 2]
+  v += dpp_mov<0x4E, 0xF>(v);   // quad_perm [2, 3, 0, 1]
+  v += dpp_mov<0x141, 0xF>(v);  // row_half_mirror
+  v += dpp_mov<0x140, 0xF>(v);  // row_mirror
+  v += dpp_mov<0x142, 0xA>(v);  // row_bcast:15 into rows 1 and 3
+  return v;
+}
+
 // dst[k] += sum over the C lanes of the group (lane index c) of v[k], k < N.
 template <int N>
 __device__ inline void add_group_sums(float (&v)[N], int C, int c, float* dst) {
@@ -780,8 +796,13 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
       for (int m = 0; m < 2 * l + 1; ++m) {
         gw += gV[l * l + m] * in.V[l * l + m];
         float part = w0 * gV[l * l + m];
-        for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-        if (c == 0) gYr[l * l + m] = part;
+        if constexpr (CC == 32) {
+          part = sum32_dpp(part);
+          if (c == 31) gYr[l * l + m] = part;
+        } else {
+          for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
+          if (c == 0) gYr[l * l + m] = part;
+        }
       }
       gwr[l * C] = gw;
     }
