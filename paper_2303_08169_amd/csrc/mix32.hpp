@@ -155,10 +155,12 @@ struct BwdB {
 };
 
 // Forward mixing of one group of EPB edges (rows (edge, m)) from T in LDS
-// ([edge][NT][CP]) straight to V_t in HBM.
+// ([edge][NT][CP]) straight to V_t in HBM, through a buffer over the group's
+// rows below ne (stores past them are dropped: no branches around them).
 template <int KIND, int W>
 __device__ inline void mix_fwd(const FwdB<KIND, W>& B, const float* Tl, int64_t e0, int64_t ne,
                                float* __restrict__ vout, int lane) {
+  const __amdgpu_buffer_rsrc_t VR = buffer_rsrc(vout + e0 * NY * C, (ne - e0 < EPB ? ne - e0 : EPB) * NY * C * 4);
 #pragma unroll
   for (int j = 0; j < kFwdN[W]; ++j) {
     const int l3 = kFwd[W][j].l3, ct = kFwd[W][j].ct, nm = 2 * l3 + 1, R = EPB * nm;
@@ -178,10 +180,8 @@ __device__ inline void mix_fwd(const FwdB<KIND, W>& B, const float* Tl, int64_t 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int rr = rt * 16 + 4 * (lane >> 4) + q;
-        if (rr < R) {
-          const int64_t e = e0 + rr / nm;
-          if (e < ne) vout[(e * NY + l3 * l3 + rr % nm) * C + n] = acc[q];
-        }
+        const unsigned off = rr < R ? (unsigned)(((rr / nm) * NY + l3 * l3 + rr % nm) * C + n) * 4 : kOutOfRange;
+        buf_store(acc[q], VR, off);
       }
     }
   }

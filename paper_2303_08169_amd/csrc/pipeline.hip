@@ -530,17 +530,19 @@ __device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int ctr, int c
 // T = C (V (x) Gamma_i) for one (edge, channel), path by path (zero
 // coefficients skipped at compile time): each component goes straight to the
 // edge's LDS rows Trow (stride CP; zero for a row past the last edge), the
-// scalar paths of a valid edge also to s. CC: channel count if known at
-// compile time, else 0.
+// scalar paths also to s through a buffer over the group's valid rows S (the
+// edge is row el of the group; stores past them are dropped, so no branch
+// makes the compiler's wait counts for the prefetched loads inexact). CC:
+// channel count if known at compile time, else 0.
 template <int LMAX, int CC>
-__device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, int c, float* Trow, int CP,
-                                   const TpFwdIn<LMAX>& in) {
+__device__ inline void tp_fwd_edge(const TpFwdArgs& a, __amdgpu_buffer_rsrc_t S, int el, bool valid, int c,
+                                   float* Trow, int CP, const TpFwdIn<LMAX>& in) {
   const int C = CC > 0 ? CC : a.C;
   constexpr int NY = TPSize<LMAX>::NY;
   float V[NY];
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) V[lm] = vprev_value(a.first, in.V, in.W, lm);
-  float* srow = a.s + e * a.lds + c;
+  const unsigned srow = (unsigned)(el * a.lds + c) * 4;
   for_paths<LMAX>(a.last, [&](int l1, int l2, int l3, int toff, int qs, int) {
 #pragma unroll
     for (int m3 = 0; m3 < 2 * l3 + 1; ++m3) {
@@ -553,7 +555,7 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, int64_t e, bool valid, in
           if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
       Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;
-      if (l3 == 0 && valid) srow[qs * C] = acc;
+      if (l3 == 0) buf_store(acc, S, srow + (unsigned)(qs * C) * 4);
     }
   });
 }
@@ -597,8 +599,9 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
     ctr = a.ei[edge_of(clampg(grp + gridDim.x))];
   }
   for (; grp < ngroups; grp += gridDim.x) {
-    const int64_t e = grp * epb + el;
-    tp_fwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, e < ne, c, Tl + el * NT * CP, CP, in);
+    const int64_t e = grp * epb + el, e0 = grp * epb;
+    const __amdgpu_buffer_rsrc_t S = buffer_rsrc(a.s + e0 * a.lds, (ne - e0 < epb ? ne - e0 : epb) * a.lds * 4);
+    tp_fwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, S, el, e < ne, c, Tl + el * NT * CP, CP, in);
     issue(clampg(grp + gridDim.x), ctr, in);
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     if (a.last) continue;
@@ -745,8 +748,8 @@ __device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int ctr, int c
 // on every outstanding load of the next group). CC: channel count if known at
 // compile time.
 template <int LMAX, int CC>
-__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const float* gTrow, int CP,
-                                   const TpBwdIn<LMAX>& in) {
+__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int nval, int el, int c, const float* gTrow,
+                                   int CP, const TpBwdIn<LMAX>& in) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = CC > 0 ? CC : a.C;
   float gV[NY], gG[NY], V[NY];
@@ -774,37 +777,64 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e, int c, const f
         }
     }
   });
-  float* ggr = a.ggc + e * (NY * C) + c;
+  if constexpr (CC == 32) {
+    // 32-channel plan (called for valid rows only): plain stores, which keep
+    // its register peak lower than buffer offsets do
+    const int64_t e = e0 + el;
+    float* ggr = a.ggc + e * (NY * C) + c;
 #pragma unroll
-  for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = gG[lm];
-  if (!a.first) {
-    float* gvr = a.gvout + e * (NY * C) + c;
+    for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = gG[lm];
+    if (!a.first) {
+      float* gvr = a.gvout + e * (NY * C) + c;
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) gvr[lm * C] = gV[lm];
-  } else {
-    // V0[c][lm] = w0[l][c] Y[lm]. The channel sums for dE/dY reduce each
-    // component right away: gathering all of them first for add_group_sums
-    // raises the register peak of the 32-channel kernel into spills.
-    // (the first layer's raw inputs: in.V holds Y, in.W holds w0)
-    float* gwr = a.gew + e * a.ldgew + c;
-    float* gYr = a.gY + e * a.ldgy;
+      for (int lm = 0; lm < NY; ++lm) gvr[lm * C] = gV[lm];
+    } else {
+      // (the first layer's raw inputs: in.V holds Y, in.W holds w0)
+      float* gwr = a.gew + e * a.ldgew + c;
+      float* gYr = a.gY + e * a.ldgy;
 #pragma unroll
-    for (int l = 0; l <= LMAX; ++l) {
-      float gw = 0.f;
-      const float w0 = in.W[l];
+      for (int l = 0; l <= LMAX; ++l) {
+        float gw = 0.f;
+        const float w0 = in.W[l];
 #pragma unroll
-      for (int m = 0; m < 2 * l + 1; ++m) {
-        gw += gV[l * l + m] * in.V[l * l + m];
-        float part = w0 * gV[l * l + m];
-        if constexpr (CC == 32) {
-          part = sum32_dpp(part);
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          gw += gV[l * l + m] * in.V[l * l + m];
+          const float part = sum32_dpp(w0 * gV[l * l + m]);
           if (c == 31) gYr[l * l + m] = part;
-        } else {
-          for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
-          if (c == 0) gYr[l * l + m] = part;
         }
+        gwr[l * C] = gw;
       }
-      gwr[l * C] = gw;
+    }
+  } else {
+    // stores through buffers over the group's nval valid rows (edge el of
+    // the group; a row past the last edge is dropped), so no branch guards them
+    const unsigned rowc = (unsigned)(el * NY * C + c) * 4;
+    const __amdgpu_buffer_rsrc_t GG = buffer_rsrc(a.ggc + e0 * (NY * C), (int64_t)nval * NY * C * 4);
+#pragma unroll
+    for (int lm = 0; lm < NY; ++lm) buf_store(gG[lm], GG, rowc + (unsigned)(lm * C) * 4);
+    if (!a.first) {
+      const __amdgpu_buffer_rsrc_t GV = buffer_rsrc(a.gvout + e0 * (NY * C), (int64_t)nval * NY * C * 4);
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) buf_store(gV[lm], GV, rowc + (unsigned)(lm * C) * 4);
+    } else {
+      // V0[c][lm] = w0[l][c] Y[lm]; each component's channel sum is reduced
+      // right away (gathering them first raises the register peak)
+      const __amdgpu_buffer_rsrc_t GW = buffer_rsrc(a.gew + e0 * a.ldgew, (int64_t)nval * a.ldgew * 4);
+      const __amdgpu_buffer_rsrc_t GY = buffer_rsrc(a.gY + e0 * a.ldgy, (int64_t)nval * a.ldgy * 4);
+      const unsigned gwo = (unsigned)(el * a.ldgew + c) * 4, gyo = (unsigned)(el * a.ldgy) * 4;
+#pragma unroll
+      for (int l = 0; l <= LMAX; ++l) {
+        float gw = 0.f;
+        const float w0 = in.W[l];
+#pragma unroll
+        for (int m = 0; m < 2 * l + 1; ++m) {
+          gw += gV[l * l + m] * in.V[l * l + m];
+          float part = w0 * gV[l * l + m];
+          for (int o = C / 2; o >= 1; o >>= 1) part += __shfl_xor(part, o, C);
+          buf_store(part, GY, c == 0 ? gyo + (unsigned)(l * l + m) * 4 : kOutOfRange);
+        }
+        buf_store(gw, GW, gwo + (unsigned)(l * C) * 4);
+      }
     }
   }
 }
@@ -872,7 +902,15 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     TpBwdIn<LMAX> inn;
     issue(clampg(grp + gridDim.x), ctr, gvn, inn);
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
-    if (valid) tp_bwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e, c, gTl + el * NT * CP, CP, in);
+    // Generic plan: every thread runs the adjoint (a row past the last edge
+    // reads the last edge's inputs) and its stores are dropped, so no branch
+    // guards the stores. The 32-channel plan keeps the branch: running the
+    // extra rows there costs more registers (spills) than the exact wait
+    // counts save.
+    const int64_t e0 = grp * epb;
+    const int nval = (int)(ne - e0 < epb ? ne - e0 : epb);
+    if (MW < 0 || valid)
+      tp_bwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
     in = inn;
