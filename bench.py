@@ -195,6 +195,9 @@ def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
     Z = torch.tensor(z, dtype=torch.int32, device=dev)
     pot.neighbor_build(P, box, skin=args.md_skin)
     E, F = pot.energy_forces(P, Z, box)
+    if not args.no_autotune:
+        # the captured step replays the tuned kernel choice
+        pot.autotune(P, Z, box, reps=3)
     ep = torch.zeros(chunk, dtype=torch.float64, device=dev)
     ek = torch.zeros(chunk, dtype=torch.float64, device=dev)
     epot, ekin, err = [], [], None

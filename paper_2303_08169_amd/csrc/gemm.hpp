@@ -490,6 +490,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int NE = NTW;                // float4 output chunks per thread (RT * 8 NTW * 16 / 4 / 512)
   __shared__ __attribute__((aligned(16))) float Os[EPI == 1 ? RT * LDO : 4];
   constexpr bool ADD = EMODE == E_ADD && EPI == 1;  // the accumulated rows are staged like A
+  constexpr bool GU = GR && KS == 8;  // dE/du row sums (the launcher passes gu only when Kp = 256)
+  __shared__ float Rd[GU ? 2 : 1][GU ? RT * 64 : 4];
   __shared__ __attribute__((aligned(16))) float Is[ADD ? 2 : 1][ADD ? RT * LDO : 4];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int64_t nrows = *nrows_p;
@@ -534,10 +536,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const float* brs = ld.rs ? ld.rs + row0 * ld.rs_ld : ld.p1;
     const int rsl = ld.rs ? ld.rs_ld : 0;
     if constexpr (RS) S.ru = ep.rs[(row0 + (t % RT < lim ? t % RT : lim)) * ep.rs_ld];
-    if constexpr (GR && KS == 8) {
-      const int w = t / 64, l = t % 64;
-      S.ru = buf_load(gu_rsrc(row0), l < 2 ? (unsigned)(w + 8 * l) * 4 : kOutOfRange);
-    }
+    if constexpr (GU) S.ru = buf_load(gu_rsrc(row0), (unsigned)(t % RT) * 4);
     if constexpr (ADD) {
       const int cpr = ep.N0 / 4;
       const float* bo = ep.o0 + row0 * ep.ld0;
@@ -572,7 +571,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     float* xdst = Xs[XIN ? it1 : 0];
     float* udst = Us[it1];
     const int64_t row0 = tile * RT;
-    if (RS && t < RT) udst[t] = S.ru;
+    if ((RS || GU) && t < RT) udst[t] = S.ru;
     if constexpr (ADD) {
       const int cpr = ep.N0 / 4;
 #pragma unroll
@@ -618,20 +617,9 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         *reinterpret_cast<bf16x4*>(&dst[rr * LDH + k]) = hi;
         if constexpr (H == 2) *reinterpret_cast<bf16x4*>(&dst[RT * LDH + rr * LDH + k]) = lo;
       }
-      if constexpr (GR && KS == 8) {  // (the launcher passes gu only when Kp = 256)
-        // the 64 lanes hold the row's chunks in order; sum them as k_gemm
-        // does (per 8-lane group sequentially over its 8 K steps, then across
-        // the group), so dE/du is bitwise identical too
-        float r8 = 0.f;
-#pragma unroll
-        for (int s = 0; s < 8; ++s) r8 += __shfl(rd, s * 8 + (lane & 7));
-#pragma unroll
-        for (int o = 1; o < 8; o <<= 1) r8 += __shfl_xor(r8, o);
-        // one lane adds the row's sum; without gu the buffer is empty
-        // (lane q holds the row's dE/du, loaded with the tile)
-        const unsigned off = lane == q ? (unsigned)rr * 4 : kOutOfRange;
-        buf_store(S.ru + ld.c * r8, gu_rsrc(row0), off);
-      }
+      // the row's chunk shares of dE/du, in chunk order (a wavefront's 64
+      // lanes hold one row: Kp = 256); the tile's iteration adds them up
+      if constexpr (GU) Rd[it1][rr * 64 + lane] = rd;
     }
   };
 
@@ -668,6 +656,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
         for (int j = 0; j < NTW; ++j) acc[j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ahi, bw[j][s][0], acc[j], 0, 0, 0);
       }
+    }
+    if constexpr (GU) {
+      // dE/du of the tile's rows (staged with the tile): row t's 64 chunk
+      // shares summed as k_gemm sums them (per 8-chunk group sequentially
+      // over the 8 K steps, then pairwise across the groups), so dE/du is
+      // bitwise identical too; the store is unconditional (dropped for t >= 16)
+      float val = 0.f;
+      unsigned off = kOutOfRange;
+      if (t < RT) {
+        const float* rp = Rd[it & 1] + t * 64;
+        float r[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) r[j] = 0.f;
+#pragma unroll
+        for (int s2 = 0; s2 < 8; ++s2)
+#pragma unroll
+          for (int j = 0; j < 8; ++j) r[j] += rp[s2 * 8 + j];
+        val = Us[it & 1][t] + ld.c * (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7])));
+        off = (unsigned)t * 4;
+      }
+      buf_store(val, gu_rsrc(tile * RT), off);
     }
     if constexpr (EPI == 0) {
       // epilogue: lane holds rows 4 (ln / 16) + q, column ln % 16 of each
