@@ -569,7 +569,9 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, __amdgpu_buffer_rsrc_t S,
 template <int KIND, int LMAX, int MW>
 __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   constexpr int NT = TPSize<LMAX>::NT;
-  const int C = MW >= 0 ? mix32::C : a.C;
+  // MW = -2: the last layer (no mixing) of a 32-channel model
+  constexpr int CC = MW >= 0 || MW == -2 ? mix32::C : 0;
+  const int C = CC > 0 ? CC : a.C;
   const int epb = 256 / C, CP = C + 4;
   const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
   float* Tl = nq_dyn_lds;
@@ -589,7 +591,7 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   };
   auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
   auto issue = [&](int64_t g, int ctr, TpFwdIn<LMAX>& inr) {
-    tp_fwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, edge_of(g), ctr, c, inr);
+    tp_fwd_load<LMAX, CC>(a, edge_of(g), ctr, c, inr);
   };
   TpFwdIn<LMAX> in;
   int64_t grp = blockIdx.x;
@@ -601,10 +603,10 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el, e0 = grp * epb;
     const __amdgpu_buffer_rsrc_t S = buffer_rsrc(a.s + e0 * a.lds, (ne - e0 < epb ? ne - e0 : epb) * a.lds * 4);
-    tp_fwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, S, el, e < ne, c, Tl + el * NT * CP, CP, in);
+    tp_fwd_edge<LMAX, CC>(a, S, el, e < ne, c, Tl + el * NT * CP, CP, in);
     issue(clampg(grp + gridDim.x), ctr, in);
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
-    if (a.last) continue;
+    if (MW == -2 || a.last) continue;
     __syncthreads();
     if constexpr (MW >= 0)
       mix32::mix_fwd<KIND, MW>(B, Tl, grp * epb, ne, a.vout, lane);
@@ -612,6 +614,12 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
       mix_fwd<KIND, LMAX>(Tl, epb, C, grp * epb, ne, a.W, a.vout);
     __syncthreads();
   }
+}
+
+// Last layer of a 32-channel l <= 2 model (no mixing; see k_tp_bwd_last32).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_tp_fwd_last32(TpFwdArgs a) {
+  tp_fwd_loop<KIND, 2, -2>(a);
 }
 
 // Forward tensor product of one layer: s (scalar paths) and, for t < T, the
@@ -845,7 +853,10 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int nval, int
 template <int KIND, int LMAX, int MW>
 __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   constexpr int NY = TPSize<LMAX>::NY, NT = TPSize<LMAX>::NT;
-  const int C = MW >= 0 ? mix32::C : a.C;
+  // MW = -2: the last layer (no mixing) of a 32-channel model
+  constexpr int CC = MW >= 0 || MW == -2 ? mix32::C : 0;
+  constexpr bool LAST = MW == -2;
+  const int C = CC > 0 ? CC : a.C;
   const int epb = 256 / C, CP = C + 4;
   const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
   float* gVl = nq_dyn_lds;
@@ -870,12 +881,12 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
   auto issue = [&](int64_t g, int ctr, float (&gvr)[NY], TpBwdIn<LMAX>& inr) {
     const int64_t ec = edge_of(g);
-    if (!a.last) {
+    if (!LAST && !a.last) {
       const float* src = a.gvin + ec * (NY * C) + c;
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) gvr[lm] = src[lm * C];
     }
-    tp_bwd_load<LMAX, (MW >= 0 ? mix32::C : 0)>(a, ec, ctr, c, inr);
+    tp_bwd_load<LMAX, CC>(a, ec, ctr, c, inr);
   };
   int64_t grp = blockIdx.x;
   int ctr = 0;
@@ -886,7 +897,7 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el;
     const bool valid = e < ne;
-    if (!a.last) {
+    if (!LAST && !a.last) {
       // The previous group's reads of gTl finished before this barrier pair
       // lets the mixing overwrite it.
 #pragma unroll
@@ -909,12 +920,19 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     // counts save.
     const int64_t e0 = grp * epb;
     const int nval = (int)(ne - e0 < epb ? ne - e0 : epb);
-    if (MW < 0 || valid)
-      tp_bwd_edge<LMAX, (MW >= 0 ? mix32::C : 0)>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
+    if (CC == 0 || valid)
+      tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
 #pragma unroll
     for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
     in = inn;
   }
+}
+
+// Last layer of a 32-channel l <= 2 model: no mixing, the channel count known
+// at compile time (fewer registers than the generic kernel).
+template <int KIND>
+__global__ __launch_bounds__(256) void k_tp_bwd_last32(TpBwdArgs a) {
+  tp_bwd_loop<KIND, 2, -2>(a);
 }
 
 // Adjoint of one layer's tensor product and, for t < T, of its channel mixing.
@@ -1344,11 +1362,13 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
   const double bpe = vin + 4.0 + 4.0 * d.nscal * d.C + (last ? 0.0 : 4.0 * d.NY * d.C);
   const int sp = span_begin(ctx, "tp_fwd" + std::to_string(t), m->tp_flop_fwd[t - 1], bpe, 0,
                             4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
-  // the last layer has no mixing: the lighter generic kernel keeps more waves
-  const bool c32 = d.L == 2 && d.C == mix32::C && !last;
+  // the last layer has no mixing: a lighter kernel keeps more waves
+  const bool c32 = d.L == 2 && d.C == mix32::C && !last, l32 = d.L == 2 && d.C == mix32::C && last;
 #define NQ_TPF(K, LM)                                                                             \
   if (LM == 2 && c32)                                                                             \
     k_tp_fwd<K, 2, true><<<tp_grid(ctx, k_tp_fwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else if (LM == 2 && l32)                                                                        \
+    k_tp_fwd_last32<K><<<tp_grid(ctx, k_tp_fwd_last32<K>, lds, d.C), 256, lds, ctx->stream>>>(a); \
   else                                                                                            \
     k_tp_fwd<K, LM, false><<<tp_grid(ctx, k_tp_fwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
@@ -1380,11 +1400,13 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const double bpe = (last ? 0.0 : 4.0 * d.NY * d.C) + vin + 4.0 + 4.0 * d.nscal * d.C + 4.0 * d.NY * d.C + vout;
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1], bpe, 0,
                             4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
-  // the last layer has no mixing: the lighter generic kernel keeps more waves
-  const bool c32 = d.L == 2 && d.C == mix32::C && !last;
+  // the last layer has no mixing: a lighter kernel keeps more waves
+  const bool c32 = d.L == 2 && d.C == mix32::C && !last, l32 = d.L == 2 && d.C == mix32::C && last;
 #define NQ_TPB(K, LM)                                                                             \
   if (LM == 2 && c32)                                                                             \
     k_tp_bwd<K, 2, true><<<tp_grid(ctx, k_tp_bwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else if (LM == 2 && l32)                                                                        \
+    k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, lds, d.C), 256, lds, ctx->stream>>>(a); \
   else                                                                                            \
     k_tp_bwd<K, LM, false><<<tp_grid(ctx, k_tp_bwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
