@@ -70,9 +70,7 @@ struct ALoad {
   // leading dimensions are multiples of 4, so each access is one aligned
   // 16-byte load). r must be a valid row; a column beyond the source width
   // reads column 0 and is zeroed by finish(). Only uniform branches, so the
-  // loads of several K steps can be in flight together. NG: the mode is known
-  // not to be A_GRADSILU (its extra registers are then not needed).
-  template <bool NG = false>
+  // loads of several K steps can be in flight together.
   __device__ inline void fetch(int64_t r, int k, ARaw& o) const {
     if (mode == A_CAT) {
       const bool second = k >= K0;
@@ -82,7 +80,7 @@ struct ALoad {
     } else {
       const int kk = k < K0 ? k : 0;
       o.v = *reinterpret_cast<const float4*>(p0 + r * ld0 + kk);
-      if (!NG && mode == A_GRADSILU) {
+      if (mode == A_GRADSILU) {
         o.a = *reinterpret_cast<const float4*>(p1 + r * ld1 + kk);
         o.f = rs ? rs[r * rs_ld] : 1.f;
       }
@@ -92,7 +90,6 @@ struct ALoad {
   // SiLU, or the adjoint g * c * rowscale * SiLU'(a).
   // With gu set, rd accumulates this chunk's share of sum_k g SiLU(a), the
   // derivative with respect to the row scale, from the same loaded values.
-  template <bool NG = false>
   __device__ inline float4 finish(const ARaw& o, bool row_ok, int k, float& rd) const {
     const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
     float4 v = o.v;
@@ -101,7 +98,7 @@ struct ALoad {
       v.y = siluf(v.y);
       v.z = siluf(v.z);
       v.w = siluf(v.w);
-    } else if (!NG && mode == A_GRADSILU) {
+    } else if (mode == A_GRADSILU) {
       const float f = c * o.f;
       const float sx = sigmoidf_(o.a.x), sy = sigmoidf_(o.a.y), sz = sigmoidf_(o.a.z), sw = sigmoidf_(o.a.w);
       if (gu) {

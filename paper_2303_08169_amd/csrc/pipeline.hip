@@ -1007,6 +1007,7 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
     for (int l = 0; l <= L; ++l) evv[l] = esrc[(int64_t)kc * lde + l * C + c];
   };
   float Yn[NY], evn[L + 1];
+  const __amdgpu_buffer_rsrc_t GYr = buffer_rsrc(gY + (int64_t)b * ldgy, (int64_t)(e1 - b) * ldgy * 4);
   if (b + g < e1) load(b + g, Yn, evn);
   for (int kk = b + g; kk < e1; kk += G) {
     float Y[NY], ev[L + 1], prod[NY];
@@ -1027,9 +1028,12 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
     }
     int first = 0, count = 0;
     spread_sum<NY, C>(prod, c, first, count);
+    // a lane holds at most ceil(NY / C) components; the stores are
+    // unconditional (dropped by the buffer range for slots holding none), so
+    // no branch makes the wait for the next edge's prefetched inputs inexact
 #pragma unroll
-    for (int q = 0; q < NY; ++q)
-      if (q < count) gY[(int64_t)kk * ldgy + first + q] = prod[q];
+    for (int q = 0; q < (NY + C - 1) / C; ++q)
+      buf_store(prod[q], GYr, q < count ? (unsigned)((kk - b) * ldgy + first + q) * 4 : kOutOfRange);
   }
 }
 
