@@ -554,7 +554,7 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, __amdgpu_buffer_rsrc_t S,
           const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
           if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
-      Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;
+      if (Trow) Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;  // (null: no mixing follows)
       if (l3 == 0) buf_store(acc, S, srow + (unsigned)(qs * C) * 4);
     }
   });
@@ -603,7 +603,7 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el, e0 = grp * epb;
     const __amdgpu_buffer_rsrc_t S = buffer_rsrc(a.s + e0 * a.lds, (ne - e0 < epb ? ne - e0 : epb) * a.lds * 4);
-    tp_fwd_edge<LMAX, CC>(a, S, el, e < ne, c, Tl + el * NT * CP, CP, in);
+    tp_fwd_edge<LMAX, CC>(a, S, el, e < ne, c, MW == -2 ? nullptr : Tl + el * NT * CP, CP, in);
     issue(clampg(grp + gridDim.x), ctr, in);
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     if (MW == -2 || a.last) continue;
@@ -1371,8 +1371,8 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
 #define NQ_TPF(K, LM)                                                                             \
   if (LM == 2 && c32)                                                                             \
     k_tp_fwd<K, 2, true><<<tp_grid(ctx, k_tp_fwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
-  else if (LM == 2 && l32)                                                                        \
-    k_tp_fwd_last32<K><<<tp_grid(ctx, k_tp_fwd_last32<K>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else if (LM == 2 && l32) /* no mixing: no LDS */                                                \
+    k_tp_fwd_last32<K><<<tp_grid(ctx, k_tp_fwd_last32<K>, 0, d.C), 256, 0, ctx->stream>>>(a);     \
   else                                                                                            \
     k_tp_fwd<K, LM, false><<<tp_grid(ctx, k_tp_fwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
@@ -1409,8 +1409,8 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
 #define NQ_TPB(K, LM)                                                                             \
   if (LM == 2 && c32)                                                                             \
     k_tp_bwd<K, 2, true><<<tp_grid(ctx, k_tp_bwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
-  else if (LM == 2 && l32)                                                                        \
-    k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, lds, d.C), 256, lds, ctx->stream>>>(a); \
+  else if (LM == 2 && l32) /* no mixing: no LDS */                                                \
+    k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, 0, d.C), 256, 0, ctx->stream>>>(a);     \
   else                                                                                            \
     k_tp_bwd<K, LM, false><<<tp_grid(ctx, k_tp_bwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (d.prec * 2 + (d.L == 2)) {
