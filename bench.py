@@ -197,7 +197,7 @@ def md_run(args, cf, pos, z, box, dt_fs=0.5, chunk=50):
     E, F = pot.energy_forces(P, Z, box)
     if not args.no_autotune:
         # the captured step replays the tuned kernel choice
-        pot.autotune(P, Z, box, reps=3)
+        pot.autotune(P, Z, box, reps=5)
     ep = torch.zeros(chunk, dtype=torch.float64, device=dev)
     ek = torch.zeros(chunk, dtype=torch.float64, device=dev)
     epot, ekin, err = [], [], None
@@ -346,7 +346,7 @@ def main():
     for mode in modes:
         pot = Potential(cf.model, w, mode)
         if not args.no_autotune:
-            rep = pot.autotune(P, Z, box, reps=3)
+            rep = pot.autotune(P, Z, box, reps=5)
             tuned[mode] = {s["name"]: s["chosen"] for s in rep["sites"]}
             log(f"{mode}: autotuned kernel variants {tuned[mode]}")
             for s_ in rep["sites"]:
