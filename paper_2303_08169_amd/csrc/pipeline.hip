@@ -868,9 +868,9 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fN) : a.W.bN, a.W.n, lane);
   }
   // Software pipeline over the workgroup's groups: the loads of the next
-  // group (dE/dV_t and the adjoint's other inputs) are issued before this
-  // group's adjoint arithmetic, so their latency overlaps it. A row past the
-  // last edge reads the last edge.
+  // group (dE/dV_t and the adjoint's other inputs) are issued right after
+  // this group's adjoint arithmetic and consumed after the next staging and
+  // mixing. A row past the last edge reads the last edge.
   float gv[NY];
   TpBwdIn<LMAX> in;
   // The centre index of a group is loaded one group earlier still.
@@ -909,10 +909,6 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
         mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, a.W);
       __syncthreads();
     }
-    float gvn[NY];
-    TpBwdIn<LMAX> inn;
-    issue(clampg(grp + gridDim.x), ctr, gvn, inn);
-    ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     // Generic plan: every thread runs the adjoint (a row past the last edge
     // reads the last edge's inputs) and its stores are dropped, so no branch
     // guards the stores. The 32-channel plan keeps the branch: running the
@@ -920,11 +916,26 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     // counts save.
     const int64_t e0 = grp * epb;
     const int nval = (int)(ne - e0 < epb ? ne - e0 : epb);
-    if (CC == 0 || valid)
-      tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
-#pragma unroll
-    for (int lm = 0; lm < NY; ++lm) gv[lm] = gvn[lm];
-    in = inn;
+    if constexpr (LAST) {
+      // no mixing follows: the next group's loads are issued before this
+      // group's adjoint so that it covers their latency
+      float gvn[NY];
+      TpBwdIn<LMAX> inn;
+      issue(clampg(grp + gridDim.x), ctr, gvn, inn);
+      ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
+      if (valid) tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
+      in = inn;
+    } else {
+      if (CC == 0 || valid)
+        tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
+      // The next group's loads go into the same registers once this group's
+      // adjoint is done: their latency then overlaps the next group's staging
+      // and mixing, and only one set of inputs is live at a time (issuing
+      // them before the adjoint kept two sets live and spilled the mixing
+      // weights).
+      issue(clampg(grp + gridDim.x), ctr, gv, in);
+      ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
+    }
   }
 }
 
