@@ -916,26 +916,15 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     // counts save.
     const int64_t e0 = grp * epb;
     const int nval = (int)(ne - e0 < epb ? ne - e0 : epb);
-    if constexpr (LAST) {
-      // no mixing follows: the next group's loads are issued before this
-      // group's adjoint so that it covers their latency
-      float gvn[NY];
-      TpBwdIn<LMAX> inn;
-      issue(clampg(grp + gridDim.x), ctr, gvn, inn);
-      ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
-      if (valid) tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
-      in = inn;
-    } else {
-      if (CC == 0 || valid)
-        tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
-      // The next group's loads go into the same registers once this group's
-      // adjoint is done: their latency then overlaps the next group's staging
-      // and mixing, and only one set of inputs is live at a time (issuing
-      // them before the adjoint kept two sets live and spilled the mixing
-      // weights).
-      issue(clampg(grp + gridDim.x), ctr, gv, in);
-      ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
-    }
+    if (CC == 0 || valid)
+      tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
+    // The next group's loads go into the same registers once this group's
+    // adjoint is done: their latency then overlaps the next group's staging
+    // and mixing (or, for the last layer, other wavefronts' work), and only
+    // one set of inputs is live at a time (issuing them before the adjoint
+    // kept two sets live and spilled the mixing weights).
+    issue(clampg(grp + gridDim.x), ctr, gv, in);
+    ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
   }
 }
 
