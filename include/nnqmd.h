@@ -229,10 +229,12 @@ nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant);
 nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes);
 
 /* Autotuner of the matrix-core products: for every per-edge MLP product of
- * one nq_energy_forces evaluation on this system, times each tile-shape
- * candidate (rows per workgroup and wave grid) over `reps` evaluations with HIP
- * events on the context's stream, and keeps the fastest for `model` (later
- * calls use it). Positions/species/cell as in nq_energy_forces. If report is
+ * one nq_energy_forces evaluation on this system, times each kernel variant
+ * (tile shapes of the tiled kernel: rows per workgroup and wave grid; where
+ * compiled for the product's shape, the two epilogue forms of the
+ * weight-stationary kernel) over `reps` evaluations with HIP events on the
+ * context's stream, and keeps the fastest for `model` (later calls, and MD
+ * graphs captured later, use it). Positions/species/cell as in nq_energy_forces. If report is
  * not NULL, a JSON object {"sites": [{"name", "np", "chosen", "ms": [...]}]} is
  * written to report[cap] (host); *len (host, may be NULL) receives its length.
  * Results of the energy/force evaluation do not depend on the choice.
