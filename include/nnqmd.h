@@ -106,16 +106,25 @@ nq_status nq_neighbor_build(nq_ctx* ctx, const double* pos, int64_t n, const dou
  * (device, FP64) with species[n] (device, int32 in [0, n_species)).
  * energy[1] (device, FP64) receives E; forces[n*3] (device, FP64) receives
  * -dE/dr; atom_energy[n] (device, FP64, or NULL) receives E_i = sum_j E_ij.
- * Uses the context's neighbour list; builds it (skin 1.0 A) if there is none
- * for this n/cell, or if an atom moved more than half the skin since the last
- * build. Returns NQ_ERR_ARG if n or cell differ from the list's and no rebuild
- * is possible. Asynchronous: nothing is synchronised. */
+ * Uses the context's neighbour list; builds it if there is none for this
+ * n/cell (list margin min(1.0 A, 0.9 (min(cell)/2 - r_c)): 1.0 A for the
+ * 27,648-atom box, 0.315 A for the 64-atom one), and rebuilds it on the device
+ * when an atom has moved more than half the margin since the last build.
+ * Returns NQ_ERR_ARG if the cutoff does not fit the minimum image.
+ * Asynchronous: nothing is synchronised, so conditions the DEVICE detects (a
+ * neighbour row longer than the row capacity during an on-device rebuild, more
+ * edges than the edge workspace holds, a non-finite coordinate or two atoms
+ * closer than 0.1 A, a species outside [0, n_species)) cannot be returned by
+ * this call: the outputs of such an evaluation are set to NaN (energy, all
+ * forces), and the next nq_stats reports the status (NQ_ERR_CAPACITY,
+ * NQ_ERR_NUMERIC, NQ_ERR_ARG). After a capacity error the next evaluation
+ * rebuilds the list on the host and grows its capacity. */
 nq_status nq_energy_forces(nq_ctx* ctx, const nq_model* model, const double* pos,
                            const int32_t* species, int64_t n, const double cell[3], double* energy,
                            double* forces, double* atom_energy);
 
 /* Energies and forces of n_rep independent replicas (ring-polymer beads of
- * the path-integral application, Sec. 4) of an n-atom system in the same box,
+ * the path-integral application, Sec. 5) of an n-atom system in the same box,
  * in one evaluation: pos[n_rep*n*3] (device, FP64, replica-major), species
  * [n_rep*n] (device, int32), energy[n_rep] (device, FP64: E of each replica),
  * forces[n_rep*n*3] (device, FP64), atom_energy[n_rep*n] (device, FP64, or
@@ -144,7 +153,7 @@ nq_status nq_energy_forces_domain(nq_ctx* ctx, const nq_model* model, const doub
                                   double* atom_energy);
 
 /* Harmonic ring-polymer coupling of the n_rep beads of every atom (the
- * path-integral replicas of Sec. 4; primitive discretisation):
+ * path-integral replicas of Sec. 5; primitive discretisation):
  *   E = 1/2 sum_a m_a w_P^2 sum_k |r_{k+1,a} - r_{k,a}|^2 (bead n_rep = bead 0),
  *   w_P = n_rep k_B T / hbar, bead separations by minimum image.
  * pos[n_rep*n*3] (device, FP64, bead-major), inv_mass[n] (device, FP64,
@@ -192,8 +201,17 @@ nq_status nq_step_nvt(nq_ctx* ctx, const nq_model* model, double* pos, double* v
 nq_status nq_force_outliers(nq_ctx* ctx, const double* forces, int64_t n, double nsigma, int32_t* count);
 
 /* Number of in-cutoff directed edges of the last nq_energy_forces / nq_step
- * evaluation, and of neighbour-list rebuilds so far. Synchronises the stream. */
+ * evaluation, and of neighbour-list rebuilds so far. Synchronises the stream.
+ * Returns (and clears) the first device-detected error of the evaluations
+ * since the last nq_stats, see nq_energy_forces. */
 nq_status nq_stats(nq_ctx* ctx, int64_t* n_edges, int64_t* n_rebuilds);
+
+/* Host-only: *captures (host) receives how many times nq_step / nq_step_nvt
+ * have captured their HIP graph on this context. A graph is captured again
+ * whenever what it bakes in changes: the caller's array pointers, n, dt, the
+ * cell, the model, the thermostat, or the context's neighbour-list geometry,
+ * row capacity and workspace buffers. For tests of that rule. */
+nq_status nq_ctx_graph_captures(const nq_ctx* ctx, int64_t* captures);
 
 /* Copy the directed in-cutoff edges (i, j) of the last evaluation, sorted by
  * (i, j), into ei[cap], ej[cap] (device, int32). *n_edges (host) receives the

@@ -25,7 +25,8 @@ from .neighbors import edge_list
 from .model import weight_segments, unpack_weights, energy_forces, EdgeTrace
 from .md import velocity_verlet, nose_hoover
 from .pimd import ring_polymer, omega_p
+from .robustness import force_outliers
 
 __all__ = ["real_sh", "real_sh_grad", "tp_paths", "clebsch_gordan", "envelope", "bessel",
            "edge_list", "weight_segments", "unpack_weights", "energy_forces", "EdgeTrace",
-           "velocity_verlet", "nose_hoover", "ring_polymer", "omega_p"]
+           "velocity_verlet", "nose_hoover", "ring_polymer", "omega_p", "force_outliers"]

@@ -5,7 +5,7 @@ TEST INFRASTRUCTURE ONLY (see the package docstring).
 The paper's application runs path-integral MD: every atom is represented by a
 number of replicas that are harmonically coupled to each other as a ring
 polymer, and the replicas' energies and forces are independent evaluations of
-the potential (Sec. 4). The paper prints no coupling formula; this module uses
+the potential (Sec. 5). The paper prints no coupling formula; this module uses
 the standard primitive discretisation, written out directly:
 
   E_spring = 1/2 sum_a m_a w_P^2 sum_{k=0}^{P-1} |r_{k+1,a} - r_{k,a}|^2,  r_P = r_0,

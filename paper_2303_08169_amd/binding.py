@@ -21,7 +21,7 @@ EXPORTS = ["nq_ctx_create", "nq_ctx_set_stream", "nq_ctx_destroy", "nq_model_wei
            "nq_model_create", "nq_model_destroy", "nq_neighbor_build", "nq_energy_forces",
            "nq_energy_forces_replicas", "nq_energy_forces_domain", "nq_ring_polymer", "nq_step",
            "nq_step_nvt", "nq_force_outliers",
-           "nq_stats", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_ctx_set_variant", "nq_autotune", "nq_timing",
+           "nq_stats", "nq_ctx_graph_captures", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_ctx_set_variant", "nq_autotune", "nq_timing",
            "nq_timing_report",
            "nq_status_str", "nq_last_error"]
 
@@ -91,6 +91,7 @@ def lib():
         "nq_step_nvt": (C.c_int, [vp, vp, vp, vp, vp, vp, i64, P(dbl), dbl, i32, dbl, dbl, vp, vp, vp, vp, vp]),
         "nq_force_outliers": (C.c_int, [vp, vp, i64, dbl, vp]),
         "nq_stats": (C.c_int, [vp, P(i64), P(i64)]),
+        "nq_ctx_graph_captures": (C.c_int, [vp, P(i64)]),
         "nq_edges_export": (C.c_int, [vp, vp, vp, i64, P(i64)]),
         "nq_debug_export": (C.c_int, [vp, vp, C.c_char_p, vp, i64, P(i64), P(i64)]),
         "nq_ctx_set_workspace_budget": (C.c_int, [vp, i64]),

@@ -88,6 +88,7 @@ void check_flags(nq_ctx* ctx) {
   }
   if (f[0] > 0) {
     zero_flags(ctx);
+    ctx->nl.built = false;  // the list is truncated: the next evaluation rebuilds (and grows) it
     throw Error{NQ_ERR_CAPACITY, "a neighbour-list row overflowed (" + std::to_string(f[0]) + " > " +
                                      std::to_string(ctx->nl.k_max) + ")"};
   }
@@ -97,6 +98,7 @@ void check_flags(nq_ctx* ctx) {
   }
   if (f[4] > 0) {
     zero_flags(ctx);
+    ctx->nl.built = false;  // the edge workspace is resized from a fresh host-visible build
     throw Error{NQ_ERR_CAPACITY, "edge workspace overflowed (" + std::to_string(f[4]) + " edges)"};
   }
 }
@@ -122,6 +124,7 @@ void neighbor_build_sync(nq_ctx* ctx, const double* pos, int64_t n, const double
     NQ_REQUIRE(nl.k_max <= 2048, NQ_ERR_CAPACITY, "neighbour rows longer than 2048");
     nl.nbr.release();
     nl.nbr.ensure((size_t)n * nl.k_max * 4);
+    ++ctx->gen;
   }
   std::vector<int> cnt(n);
   NQ_HIP(hipMemcpy(cnt.data(), nl.nbr_cnt.p, n * sizeof(int), hipMemcpyDeviceToHost));
@@ -377,7 +380,7 @@ void md_run(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const 
                                   (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
                                   (const void*)(intptr_t)ctx->ws.chunks.size(),
                                   ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p,
-                                  ctx->md_scratch.p};
+                                  ctx->md_scratch.p, (const void*)(intptr_t)ctx->gen};
   auto push_double = [&](double v) {
     int64_t b;
     std::memcpy(&b, &v, sizeof(double));
@@ -428,6 +431,7 @@ void md_run(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const 
     }
     ctx->stream = user;
     ctx->graph_key = key;
+    ++ctx->graph_captures;
   }
   NQ_HIP(hipEventRecord(ctx->ev[0], user));
   NQ_HIP(hipStreamWaitEvent(ctx->md_stream, ctx->ev[0], 0));
@@ -466,6 +470,13 @@ nq_status nq_step_nvt(nq_ctx* ctx, const nq_model* model, double* pos, double* v
     nh.state = thermostat;
     nh.ethermo = ethermo;
     md_run(ctx, model, pos, vel, inv_mass, species, n, cell, dt_fs, n_steps, forces, epot, ekin, &nh);
+  });
+}
+
+nq_status nq_ctx_graph_captures(const nq_ctx* ctx, int64_t* captures) {
+  return guarded(nullptr, [&] {
+    NQ_REQUIRE(ctx && captures, NQ_ERR_ARG, "null argument");
+    *captures = ctx->graph_captures;
   });
 }
 

@@ -138,7 +138,7 @@ __global__ __launch_bounds__(1024) void k_force_outliers(const double* __restric
 __device__ inline double mic(double d, double L) { return d - L * rint(d / L); }
 
 // Harmonic coupling of the R beads (replicas) of every atom into a ring
-// (the path-integral ring polymer of the application in paper Sec. 4):
+// (the path-integral ring polymer of the application in paper Sec. 5):
 //   E = 1/2 sum_a m_a w^2 sum_k |r_{k+1,a} - r_{k,a}|^2,  bead R = bead 0,
 //   F_{k,a} += m_a w^2 ((r_{k-1,a} - r_{k,a}) + (r_{k+1,a} - r_{k,a})),
 // bead separations by minimum image. One thread per (bead, atom); e_bond gets

@@ -314,6 +314,7 @@ void nbr_configure(nq_ctx* ctx, int64_t n, const double cell[3], double r_cut, d
   const bool same = nl.n == n && nl.n_rep == n_rep && nl.box[0] == cell[0] && nl.box[1] == cell[1] &&
                     nl.box[2] == cell[2] && nl.r_cut == r_cut && nl.skin == skin;
   if (same && nl.k_max > 0) return;
+  ++ctx->gen;
   nl.n = n;
   nl.n_rep = n_rep;
   for (int k = 0; k < 3; ++k) {

@@ -192,6 +192,11 @@ struct nq_ctx {
   hipEvent_t ev[2] = {nullptr, nullptr};
   hipGraphExec_t graph_exec = nullptr;
   std::vector<const void*> graph_key;
+  // Bumped whenever device buffers or sizes that a captured graph bakes in
+  // change (neighbour-list geometry or row capacity, workspace reallocation);
+  // part of the graph key, so such a change forces a new capture.
+  int64_t gen = 0;
+  int64_t graph_captures = 0;
   nq::DevBuf md_scratch;
   nq::DevBuf rp_scratch;  // ring-polymer bond energies
   int64_t last_edges = 0;

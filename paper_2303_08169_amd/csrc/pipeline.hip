@@ -668,10 +668,19 @@ __global__ void k_atom_energy(int64_t n, const int* __restrict__ nedge_p, const 
   if (out) out[a] = s;
 }
 
+// True when the device has flagged a condition that makes this evaluation's
+// results wrong (a truncated neighbour row or edge list, a non-finite
+// coordinate or coincident atoms, a species out of range): the outputs are
+// then poisoned with NaN, so an error reported only at the next nq_stats is
+// still visible in the results.
+__device__ inline bool results_invalid(const int* flags) {
+  return (flags[0] > 0) | (flags[2] != 0) | (flags[4] > 0) | (flags[5] != 0);
+}
+
 // Neumaier-compensated FP64 sums of consecutive segments of n values, one
 // block per segment (one segment per replica): energy[b] = sum of v[b n, (b+1) n).
 __global__ __launch_bounds__(1024) void k_total_energy(int64_t n, const double* __restrict__ v,
-                                                       double* __restrict__ energy) {
+                                                       double* __restrict__ energy, const int* __restrict__ flags) {
   __shared__ double hs[1024], hc[1024];
   double s = 0.0, c = 0.0;
   v += (int64_t)blockIdx.x * n;
@@ -695,7 +704,7 @@ __global__ __launch_bounds__(1024) void k_total_energy(int64_t n, const double* 
     }
     __syncthreads();
   }
-  if (threadIdx.x == 0) energy[0] = hs[0] + hc[0];
+  if (threadIdx.x == 0) energy[0] = results_invalid(flags) ? __builtin_nan("") : hs[0] + hc[0];
 }
 
 // ------------------------------------------------------------------ adjoint helpers
@@ -1109,9 +1118,13 @@ __global__ void k_geometry_bwd(const int* __restrict__ nedge_p, const float* __r
 __global__ void k_forces(int64_t n, int64_t n_centres, const int* __restrict__ nedge_p,
                          const int* __restrict__ eoff, const int* __restrict__ ej, const int* __restrict__ rev,
                          const int* __restrict__ nbr, const int* __restrict__ nbr_cnt, int k_max,
-                         const float4* __restrict__ gr, double* __restrict__ F) {
+                         const float4* __restrict__ gr, double* __restrict__ F, const int* __restrict__ flags) {
   const int64_t a = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (a >= n) return;
+  if (results_invalid(flags)) {
+    F[3 * a] = F[3 * a + 1] = F[3 * a + 2] = __builtin_nan("");
+    return;
+  }
   const int ne = *nedge_p;
   double fx = 0, fy = 0, fz = 0;
   if (a < n_centres) {
@@ -1496,6 +1509,7 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
   cap_all = rup(std::max<int64_t>(cap_all, 1), 128);
   const NbrList& nl = ctx->nl;
   if (ws.model == m && ws.cap_all >= cap_all && ws.n_atoms == n_atoms && !ws.chunks.empty()) return;
+  ++ctx->gen;
   const Dims& d = m->dims;
   NQ_HIP(hipStreamSynchronize(ctx->stream));
   ws.bufs.clear();
@@ -1797,13 +1811,14 @@ void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces
   hipStream_t s = ctx->stream;
   const int64_t n = ws.n_atoms;
   int sp = span_begin(ctx, "total_energy");
-  k_total_energy<<<(unsigned)n_rep, 1024, 0, s>>>(n / n_rep, ws.atomE, energy);
+  k_total_energy<<<(unsigned)n_rep, 1024, 0, s>>>(n / n_rep, ws.atomE, energy, ctx->nl.flags.as<int>());
   span_end(ctx, sp);
   sp = span_begin(ctx, "forces");
   const NbrList& nl = ctx->nl;
   k_forces<<<grid_for(n, 256), 256, 0, s>>>(n, n_centres < 0 ? n : n_centres, ws.nedge.as<int>(),
                                             ws.eoff.as<int>(), ws.ej.as<int>(), ws.rev.as<int>(),
-                                            nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max, ws.gr, forces);
+                                            nl.nbr.as<int>(), nl.nbr_cnt.as<int>(), nl.k_max, ws.gr, forces,
+                                            nl.flags.as<int>());
   span_end(ctx, sp);
   NQ_HIP(hipGetLastError());
 }

@@ -198,6 +198,12 @@ class Potential:
         B.check(self.lib.nq_stats(self._ctx, C.byref(ne), C.byref(nr)), self._ctx)
         return ne.value, nr.value
 
+    def graph_captures(self) -> int:
+        """How many times nq_step / nq_step_nvt captured their HIP graph on this context."""
+        n = C.c_int64(0)
+        B.check(self.lib.nq_ctx_graph_captures(self._ctx, C.byref(n)), self._ctx)
+        return n.value
+
     def edges(self):
         ne, _ = self.stats()
         cap = max(ne, 1)

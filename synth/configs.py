@@ -3,7 +3,7 @@
 Sizes follow the liquid-ammonia systems of the paper's scaling runs (Sec. 3.3:
 6,912 atoms per GPU; single-node runs of 1,728 to 13,824 atoms) at a number
 density of 0.0965 atoms per cubic Angstrom, with the cutoff r_max = 6.0 A and
-the equivariant rank l of the model table (Sec. 4.1, Table 2; Sec. 6, Table 5).
+the equivariant rank l of the model table (Sec. 4.1, Table 2; Sec. 4.5, Table 5).
 The model widths are this project's choice (the paper does not state them).
 """
 from __future__ import annotations

@@ -44,3 +44,15 @@ def checksum(pos):
 
 def rel_rms(a, b):
     return float(np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(np.asarray(b)))
+
+
+def assert_forces_close(F, F_ref, tol, what=""):
+    """Forces within tol of the reference: relative RMS over all components, and
+    per atom max_a |F_a - F_ref,a| <= tol * RMS_a |F_ref,a| (one wrong atom cannot
+    hide in the norm of a large system)."""
+    F, F_ref = np.asarray(F).reshape(-1, 3), np.asarray(F_ref).reshape(-1, 3)
+    rr = rel_rms(F, F_ref)
+    assert rr <= tol, f"{what} force rel-RMS {rr:.3e} > {tol:.1e}"
+    rms_ref = float(np.sqrt((F_ref * F_ref).sum(1).mean()))
+    worst = float(np.linalg.norm(F - F_ref, axis=1).max())
+    assert worst <= tol * rms_ref, f"{what} worst atom {worst:.3e} > {tol:.1e} * RMS|F| {rms_ref:.3e}"

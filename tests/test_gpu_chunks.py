@@ -8,7 +8,7 @@ import pytest
 import torch
 
 import oracle
-from tests.gpu_common import TOL, rel_rms, system
+from tests.gpu_common import TOL, assert_forces_close, rel_rms, system
 
 pytestmark = pytest.mark.gpu
 
@@ -54,7 +54,7 @@ def test_big_model_sampled():
     a = int(centres[0])
     nb = oracle.edge_list(pos, L, cf.model.r_cut, centers=[a])[1]
     _, F0 = oracle.energy_forces(pos, z, L, cf.model, w, centers=np.concatenate([[a], nb]))
-    assert rel_rms(F[a], F0[a]) <= TOL["bf16x3"]["force"]
+    assert_forces_close(F[a], F0[a], TOL["bf16x3"]["force"])
     assert abs(E.item() - Ei.sum()) <= 1e-9 * np.abs(Ei).sum()
     np.testing.assert_allclose(F.sum(0), 0.0, atol=1e-6 * np.abs(F).sum())
     assert abs(ne / len(pos) - cf.model.avg_num_neighbors) < 0.05 * cf.model.avg_num_neighbors
@@ -80,16 +80,21 @@ def test_autotune_keeps_results_bitwise():
 
 @pytest.mark.parametrize("prec", ["bf16x3", "bf16"])
 def test_kernel_variants_bitwise(prec):
-    """Every kernel choice of the matrix-core products (tile shapes of the
+    """Every kernel choice of every matrix-core product (all tile shapes of the
     tiled kernel, both epilogue forms of the weight-stationary kernel) gives
-    the same bits. (The
-    27,648-atom test repeats this at a ragged edge count: 2,372,786 rows.)"""
+    the same bits. Variant v selects v modulo each product's count, so
+    v = 0 .. max count - 1 visits every variant of every product; -2 / -3 are
+    the two weight-stationary forms where compiled. (The 27,648-atom test
+    repeats this for the tuned choice at a ragged edge count.)"""
     from paper_2303_08169_amd.potential import Potential
     cf, pos, z, L, w = system("nh3_1024_l2")
     pot = Potential(cf.model, w, prec)
     P, Z = _dev(pos, z)
+    rep = pot.autotune(P, Z, L, reps=1)
+    nmax = max(len(site["ms"]) for site in rep["sites"])
+    assert nmax >= 4
     ref = None
-    for v in (0, 1, -2, -3):
+    for v in list(range(nmax)) + [-2, -3, -1]:
         pot.set_variant(v)
         E, F, Ei = pot.energy_forces(P, Z, L, atom_energy=True)
         torch.cuda.synchronize()
@@ -97,8 +102,8 @@ def test_kernel_variants_bitwise(prec):
         if ref is None:
             ref = got
         else:
-            assert got[0] == ref[0]
-            assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2])
+            assert got[0] == ref[0], v
+            assert np.array_equal(got[1], ref[1]) and np.array_equal(got[2], ref[2]), v
     from paper_2303_08169_amd.binding import NQError
     with pytest.raises(NQError):
         pot.set_variant(-4)

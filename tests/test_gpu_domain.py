@@ -4,12 +4,18 @@ The periodic 1,024-atom system is cut into two slabs; each slab is evaluated
 as owned atoms + ghost images within the cutoff in an open frame. The domain
 energies must add up to the periodic energy and the domain forces, with every
 ghost's force added back to the atom it copies (the reverse exchange), must
-reproduce the periodic forces; owned atoms' E_i must match and ghosts' be 0."""
+reproduce the periodic forces; owned atoms' E_i must match and ghosts' be 0.
+Each domain is also compared directly with the oracle evaluated on the same
+open-frame coordinates with the owned atoms as the only centres: the domain
+energy, and the forces on owned and ghost atoms."""
 import numpy as np
 import pytest
 import torch
 
-from tests.gpu_common import rel_rms, system
+import oracle
+from tests.gpu_common import TOL, assert_forces_close, system
+
+_ORACLE = {}
 
 pytestmark = pytest.mark.gpu
 
@@ -52,12 +58,18 @@ def test_two_slab_decomposition(prec):
                                               torch.tensor(z[orig], dtype=torch.int32, device="cuda"),
                                               n_own, frame, atom_energy=True)
         Ad = Ad.cpu().numpy()
+        if x0 not in _ORACLE:
+            _ORACLE[x0] = oracle.energy_forces(q, z[orig], frame, cf.model, w, centers=np.arange(n_own))
+        Eo, Fo = _ORACLE[x0]
+        assert abs(Ed.item() - Eo) <= TOL[prec]["energy"] * abs(Eo)
+        assert_forces_close(Fd.cpu().numpy()[:n_own], Fo[:n_own], TOL[prec]["force"], "owned")
+        assert_forces_close(Fd.cpu().numpy()[n_own:], Fo[n_own:], TOL[prec]["force"], "ghosts")
         assert np.all(Ad[n_own:] == 0.0)
         np.testing.assert_allclose(Ad[:n_own], A0[orig[:n_own]], rtol=1e-5, atol=1e-6 * np.abs(A0).max())
         E += Ed.item()
         np.add.at(F, orig, Fd.cpu().numpy())
     assert abs(E - E0) <= 1e-6 * abs(E0)
-    assert rel_rms(F, F0) <= 1e-5
+    assert_forces_close(F, F0, 1e-5)
     pot.close()
 
 
