@@ -173,8 +173,8 @@ def test_graph_recaptured_after_list_change():
     fresh.step(P1, V1, IM, Z, L, 0.5, 10, F1)
     torch.cuda.synchronize()
     assert torch.equal(P, P1) and torch.equal(V, V1) and torch.equal(F, F1)
-    # same pointers, same list: replayed, not captured again
-    pot.step(P, V, IM, Z, L, 0.5, 2, F)
+    # same pointers, step count and list: replayed, not captured again
+    pot.step(P, V, IM, Z, L, 0.5, 10, F)
     torch.cuda.synchronize()
     assert pot.graph_captures() == 2
     pot.close()
