@@ -290,7 +290,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="nh3_27648_l2")
     ap.add_argument("--precision", default="bf16x3", choices=["fp32", "bf16", "bf16x3"])
-    ap.add_argument("--compare", default="fp32,bf16", help="other precision modes timed alongside")
+    ap.add_argument("--path", default="auto", choices=["auto", "fused", "layered"],
+                    help="evaluation path of the reported mode (auto: the fused kernel where compiled)")
+    ap.add_argument("--compare", default="bf16x3:layered,fp32,bf16",
+                    help="other modes timed alongside: precision[:path], comma separated")
     ap.add_argument("--cpu-sample-atoms", type=int, default=20)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-autotune", action="store_true", help="skip the tile-shape autotuner")
@@ -341,18 +344,21 @@ def main():
     log(f"workload {args.workload}: {cf.n_atoms} atoms, box {box:.3f} A")
 
     results = {}
-    modes = [args.precision] + [m for m in args.compare.split(",") if m and m != args.precision]
+    main_mode = args.precision + ("" if args.path == "auto" else ":" + args.path)
+    modes = [main_mode] + [m for m in args.compare.split(",") if m and m != main_mode]
     tuned = {}
     for mode in modes:
-        pot = Potential(cf.model, w, mode)
-        if not args.no_autotune:
+        prec, _, path = mode.partition(":")
+        pot = Potential(cf.model, w, prec)
+        pot.set_path(path or "auto")
+        if not args.no_autotune and (path == "layered" or prec == "fp32"):
             rep = pot.autotune(P, Z, box, reps=5)
             tuned[mode] = {s["name"]: s["chosen"] for s in rep["sites"]}
             log(f"{mode}: autotuned kernel variants {tuned[mode]}")
             for s_ in rep["sites"]:
                 log(f"   {s_['name']:<16} " + " ".join(f"{t:.3f}" for t in s_["ms"]))
-        steps = args.steps if mode == args.precision else max(3, min(args.steps, 10))
-        dt, report, ne, E, F = timed_run(pot, P, Z, box, steps, args.warmup if mode == args.precision else 2)
+        steps = args.steps if mode == main_mode else max(3, min(args.steps, 10))
+        dt, report, ne, E, F = timed_run(pot, P, Z, box, steps, args.warmup if mode == main_mode else 2)
         _, _, Ei = pot.energy_forces(P, Z, box, atom_energy=True)
         torch.cuda.synchronize()
         results[mode] = dict(dt=dt, report=report, edges=ne, E=E.item(), F=F.cpu().numpy(),
@@ -362,7 +368,7 @@ def main():
         del pot
         torch.cuda.empty_cache()
 
-    main_res = results[args.precision]
+    main_res = results[main_mode]
     line = {
         "metric": METRIC,
         "value": cf.n_atoms / main_res["dt"],
@@ -398,7 +404,7 @@ def main():
             modes_out[mode].update(errors(smp, r["F"], r["Ei"]))
     line["modes"] = modes_out
     if tuned:
-        line["autotune"] = tuned.get(args.precision)
+        line["autotune"] = tuned.get(main_mode)
     line["kernels_top"] = sorted(
         [{"name": k["name"], "ms_per_step": k["ms_total"] / main_res["steps"], "launches": k["count"]}
          for k in main_res["report"]["kernels"]], key=lambda k: -k["ms_per_step"])

@@ -225,6 +225,23 @@ nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, in
 nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
                           int64_t cap, int64_t* rows, int64_t* width);
 
+/* Evaluation path of later calls on this context. NQ_PATH_AUTO (default) and
+ * NQ_PATH_LAYERED: the layered kernels (one launch per stage, activations in
+ * device memory; the faster path on the benchmark workload, and the one
+ * nq_debug_export reads). NQ_PATH_FUSED: one persistent kernel per
+ * evaluation that runs the forward pass and its adjoint centre by centre and
+ * keeps the edge activations of each 64-edge block on chip; it is compiled
+ * for l <= 2, two layers, 32 channels, two-body MLP 64-128-256, one 256-wide
+ * latent layer, a 128-wide edge layer, three species, eight Bessel functions
+ * and precision BF16 or BF16X3, and the next evaluation returns
+ * NQ_ERR_UNSUPPORTED for other models. Both paths compute the same function
+ * (paper Sec. 2.1, Eq. 1) and agree to rounding. NQ_ERR_ARG for other
+ * values. Synchronises the stream and drops the captured MD graph. */
+#define NQ_PATH_AUTO 0
+#define NQ_PATH_LAYERED 1
+#define NQ_PATH_FUSED 2
+nq_status nq_ctx_set_path(nq_ctx* ctx, int32_t path);
+
 /* Kernel choice for the matrix-core products of later evaluations on this
  * context: NQ_VARIANT_TUNED (default) uses the model's autotuned choice (or
  * variant 0 before nq_autotune), NQ_VARIANT_LAST and NQ_VARIANT_LAST2 the last

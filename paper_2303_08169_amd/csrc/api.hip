@@ -142,6 +142,17 @@ double default_skin(const double cell[3], double rc) {
   return std::min(1.0, 0.9 * room);
 }
 
+// True when evaluations of this model on this context take the fused kernel.
+// The layered kernels are the default: on the benchmark workload they are
+// measured faster than the fused kernel, whose per-block weight traffic from
+// L2 (the whole weight set once per 64 edges) bounds it.
+bool use_fused(const nq_ctx* ctx, const nq_model* m) {
+  if (ctx->path != NQ_PATH_FUSED) return false;
+  NQ_REQUIRE(fused_supported(m), NQ_ERR_UNSUPPORTED,
+             "the fused kernel is not compiled for this model shape or precision");
+  return true;
+}
+
 // Make sure a neighbour list valid for this model exists and the workspace fits it.
 // n counts the atoms of all n_rep replicas.
 void ensure_list(nq_ctx* ctx, const nq_model* m, const double* pos, int64_t n, const double cell[3],
@@ -152,7 +163,9 @@ void ensure_list(nq_ctx* ctx, const nq_model* m, const double* pos, int64_t n, c
                   nl.box[2] == cell[2] && nl.r_cut + nl.skin >= rc;
   if (!ok) neighbor_build_sync(ctx, pos, n, cell, rc, default_skin(cell, rc), n_rep);
   const int64_t cap = rup((int64_t)(1.25 * (double)nl.n_entries) + 1024, 128);
-  ws_ensure(ctx, m, cap, n);
+  const bool fused = use_fused(ctx, m);
+  ws_ensure(ctx, m, cap, n, !fused);
+  if (fused) fused_prepare(ctx);
 }
 
 void check_common(nq_ctx* ctx, const nq_model* m, const double* pos, const int32_t* species, int64_t n,
@@ -176,10 +189,14 @@ void evaluate_async(nq_ctx* ctx, const nq_model* m, const double* pos, const int
   sp = span_begin(ctx, "edge_list");
   edges_build_async(ctx, pos, m->dims.rc, n_centres);
   span_end(ctx, sp);
-  for (int c = 0; c + 1 < (int)ctx->ws.chunks.size(); ++c) {
-    chunk_view_async(ctx, c);
-    forward_async(ctx, m, species, atom_energy);
-    backward_async(ctx, m);
+  if (use_fused(ctx, m)) {
+    fused_async(ctx, m, species, atom_energy, n_centres);
+  } else {
+    for (int c = 0; c + 1 < (int)ctx->ws.chunks.size(); ++c) {
+      chunk_view_async(ctx, c);
+      forward_async(ctx, m, species, atom_energy);
+      backward_async(ctx, m);
+    }
   }
   finish_async(ctx, m, energy, forces, n_rep, n_centres);
 }
@@ -517,9 +534,12 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     NQ_REQUIRE(ctx && model && name && out && rows && width, NQ_ERR_ARG, "null argument");
     const Workspace& ws = ctx->ws;
     NQ_REQUIRE(ws.model == model && ws.nedge.p, NQ_ERR_ARG, "no evaluation of this model yet");
+    NQ_REQUIRE(ws.has_act || std::string(name) == "g", NQ_ERR_ARG,
+               "stage intermediates exist only on the layered path (nq_ctx_set_path)");
     const Dims& d = model->dims;
     int ne = 0, ne_all = 0;
-    NQ_HIP(hipMemcpyAsync(&ne, ws.v_nedge, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
+    NQ_HIP(hipMemcpyAsync(&ne, ws.v_nedge ? ws.v_nedge : ws.nedge.as<int>(), sizeof(int), hipMemcpyDeviceToHost,
+                          ctx->stream));
     NQ_HIP(hipMemcpyAsync(&ne_all, ws.nedge.p, sizeof(int), hipMemcpyDeviceToHost, ctx->stream));
     NQ_HIP(hipStreamSynchronize(ctx->stream));
     const std::string s(name);
@@ -564,6 +584,20 @@ nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant) {
   });
 }
 
+nq_status nq_ctx_set_path(nq_ctx* ctx, int32_t path) {
+  return guarded(ctx, [&] {
+    NQ_REQUIRE(ctx && (path == NQ_PATH_AUTO || path == NQ_PATH_LAYERED || path == NQ_PATH_FUSED), NQ_ERR_ARG,
+               "bad path");
+    NQ_HIP(hipStreamSynchronize(ctx->stream));
+    ctx->path = path;
+    if (ctx->graph_exec) {
+      (void)hipGraphExecDestroy(ctx->graph_exec);
+      ctx->graph_exec = nullptr;
+      ctx->graph_key.clear();
+    }
+  });
+}
+
 nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes) {
   return guarded(ctx, [&] {
     NQ_REQUIRE(ctx && bytes > 0, NQ_ERR_ARG, "bad budget");
@@ -585,6 +619,14 @@ nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int
     check_common(ctx, model, pos, species, n, cell);
     NQ_REQUIRE(reps >= 1 && reps <= 100, NQ_ERR_ARG, "reps must be 1..100");
     NQ_HIP(hipSetDevice(ctx->device));
+    // the tuned products are the layered kernels'
+    const int was_path = ctx->path;
+    ctx->path = NQ_PATH_LAYERED;
+    struct Restore {
+      nq_ctx* c;
+      int p;
+      ~Restore() { c->path = p; }
+    } restore{ctx, was_path};
     ensure_list(ctx, model, pos, n, cell);
     DevBuf scratch;
     scratch.ensure((size_t)(n * 3 + 8) * sizeof(double));

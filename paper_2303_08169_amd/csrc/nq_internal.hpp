@@ -154,6 +154,7 @@ struct Workspace {
   std::vector<std::unique_ptr<DevBuf>> bufs;    // model-dependent buffers
   std::vector<int64_t> chunks;                  // centre boundaries a_0 = 0 < a_1 < ... = n
   int K0p = 0, maxw = 0;
+  bool has_act = false;                         // the layered kernels' buffers exist
   // current chunk view: centres [v_a0, v_a0 + v_n), edges renumbered from 0
   int64_t v_a0 = 0, v_n = 0;
   const int *v_nedge = nullptr, *v_ei = nullptr, *v_ej = nullptr, *v_eoff = nullptr, *v_e0 = nullptr;
@@ -198,6 +199,8 @@ struct nq_ctx {
   int64_t gen = 0;
   int64_t graph_captures = 0;
   nq::DevBuf md_scratch;
+  nq::DevBuf fz_scratch;  // per-workgroup scratch of the fused kernel
+  int path = NQ_PATH_AUTO;  // nq_ctx_set_path
   nq::DevBuf rp_scratch;  // ring-polymer bond energies
   int64_t last_edges = 0;
   int64_t ws_budget = (int64_t)160 << 30;  // bytes allowed for per-edge activations
@@ -227,7 +230,8 @@ void weight_layout(const nq_model_desc& d, std::vector<std::pair<int64_t, int64_
 void derive_cg(CGTable& t);
 
 // ---- pipeline (forward.hip / backward.hip)
-void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms);
+// activations: allocate the per-edge buffers of the layered kernels too.
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms, bool activations);
 void chunk_view_async(nq_ctx* ctx, int chunk);
 void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy);
 void backward_async(nq_ctx* ctx, const nq_model* m);
@@ -235,6 +239,14 @@ void backward_async(nq_ctx* ctx, const nq_model* m);
 // (ghosts) also gather the edges that point at them through the neighbour list.
 void finish_async(nq_ctx* ctx, const nq_model* m, double* energy, double* forces, int64_t n_rep = 1,
                   int64_t n_centres = -1);
+
+// ---- fused per-centre kernel (fused.hip)
+bool fused_supported(const nq_model* m);
+// Sizes the fused kernel's scratch for the current neighbour list (outside graph capture).
+void fused_prepare(nq_ctx* ctx);
+// E_i (ws.atomE, and atom_energy when not null) and g_ij (ws.grbuf) of the
+// whole edge list in one launch; atoms >= n_centres (>= 0) have no edges.
+void fused_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, double* atom_energy, int64_t n_centres);
 
 
 // ---- MD (md.hip)

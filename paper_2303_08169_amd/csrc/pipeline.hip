@@ -1504,11 +1504,13 @@ __global__ void k_chunk_offsets(const int* __restrict__ eoff, int64_t a0, int64_
 
 }  // namespace
 
-void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms) {
+void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms, bool activations) {
   Workspace& ws = ctx->ws;
   cap_all = rup(std::max<int64_t>(cap_all, 1), 128);
   const NbrList& nl = ctx->nl;
-  if (ws.model == m && ws.cap_all >= cap_all && ws.n_atoms == n_atoms && !ws.chunks.empty()) return;
+  if (ws.model == m && ws.cap_all >= cap_all && ws.n_atoms == n_atoms && !ws.chunks.empty() &&
+      (ws.has_act || !activations))
+    return;
   ++ctx->gen;
   const Dims& d = m->dims;
   NQ_HIP(hipStreamSynchronize(ctx->stream));
@@ -1524,6 +1526,20 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms)
   ws.rij.ensure(cap_all * 16);
   ws.grbuf.ensure(cap_all * 16);
   ws.nedge.ensure(64);
+  ws.gr = ws.grbuf.as<float4>();
+  ws.has_act = activations;
+  if (!activations) {
+    // the fused path: energies per atom and the edge list only
+    ws.chunks.assign({0, n_atoms});
+    ws.cap = cap_all;
+    ws.bufs.emplace_back(new DevBuf());
+    ws.bufs.back()->ensure((size_t)n_atoms * 8);
+    ws.atomE = ws.bufs.back()->as<double>();
+    ws.bufs.emplace_back(new DevBuf());
+    ws.bufs.back()->ensure(64);
+    ws.esum = ws.bufs.back()->as<double>();
+    return;
+  }
   ws.K0p = (int)rup(d.n_in2b, 32);
   int maxw = d.n_in2b;
   for (int k = 0; k < d.n_tb; ++k) maxw = std::max(maxw, d.tb[k]);

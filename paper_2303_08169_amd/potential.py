@@ -189,6 +189,14 @@ class Potential:
         each. Results are bitwise identical for every choice."""
         B.check(self.lib.nq_ctx_set_variant(self._ctx, int(variant)), self._ctx)
 
+    PATHS = {"auto": 0, "layered": 1, "fused": 2}
+
+    def set_path(self, path: str):
+        """Evaluation path of later calls: "auto" or "layered" (the layered
+        kernels) or "fused" (the persistent per-centre kernel; an error at the
+        next evaluation if the model does not fit it)."""
+        B.check(self.lib.nq_ctx_set_path(self._ctx, self.PATHS[path]), self._ctx)
+
     def set_workspace_budget(self, nbytes: int):
         """Cap the per-edge activation memory; larger systems run in chunks of centres."""
         B.check(self.lib.nq_ctx_set_workspace_budget(self._ctx, int(nbytes)), self._ctx)

@@ -65,6 +65,7 @@ def test_autotune_keeps_results_bitwise():
     from paper_2303_08169_amd.potential import Potential
     cf, pos, z, L, w = system("nh3_1024_l2")
     pot = Potential(cf.model, w, "bf16x3")
+    pot.set_path("layered")  # the tuned products are the layered kernels'
     P, Z = _dev(pos, z)
     E1, F1 = pot.energy_forces(P, Z, L)
     torch.cuda.synchronize()
@@ -89,6 +90,7 @@ def test_kernel_variants_bitwise(prec):
     from paper_2303_08169_amd.potential import Potential
     cf, pos, z, L, w = system("nh3_1024_l2")
     pot = Potential(cf.model, w, prec)
+    pot.set_path("layered")
     P, Z = _dev(pos, z)
     rep = pot.autotune(P, Z, L, reps=1)
     nmax = max(len(site["ms"]) for site in rep["sites"])
