@@ -164,6 +164,24 @@ nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass
                           int64_t n_rep, const double cell[3], double temperature, double* forces,
                           double* energy);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * operation, arguments and results as nq_ring_polymer, with the bond energies
+ * staged in a fixed device array of NQ_RING_POLYMER_NOALLOC_MAX doubles
+ * (8 MiB) that the library holds on every GPU it runs on until the process
+ * ends, instead of context memory grown on demand. Allocates nothing: no
+ * hipMalloc, hipFree or allocating library call. NQ_ERR_CAPACITY if
+ * n * n_rep > NQ_RING_POLYMER_NOALLOC_MAX (nothing is launched), NQ_ERR_ARG as
+ * for nq_ring_polymer. Every call on one GPU, from any context, uses the same
+ * array: calls that overlap on one GPU (different streams, not ordered by
+ * events) race and give wrong energies; calls ordered on one stream do not.
+ * Nothing in the array needs to start at zero (each call writes every entry
+ * it reads). Asynchronous. */
+#define NQ_RING_POLYMER_NOALLOC_MAX ((int64_t)1 << 20)
+nq_status nq_ring_polymer_noalloc(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n,
+                                  int64_t n_rep, const double cell[3], double temperature,
+                                  double* forces, double* energy);
+
 /* n_steps velocity-Verlet steps (Eq. 1) of length dt_fs: v += dt/2 F/m;
  * r += dt v (wrapped into the box); F = F(r); v += dt/2 F/m. pos[n*3], vel[n*3]
  * (device, FP64, A and A/fs) are updated in place; inv_mass[n] (device, FP64,

@@ -19,7 +19,7 @@ PRECISION = {"fp32": 0, "bf16": 1, "bf16x3": 2}
 
 EXPORTS = ["nq_ctx_create", "nq_ctx_set_stream", "nq_ctx_destroy", "nq_model_weight_layout",
            "nq_model_create", "nq_model_destroy", "nq_neighbor_build", "nq_energy_forces",
-           "nq_energy_forces_replicas", "nq_energy_forces_domain", "nq_ring_polymer", "nq_step",
+           "nq_energy_forces_replicas", "nq_energy_forces_domain", "nq_ring_polymer", "nq_ring_polymer_noalloc", "nq_step",
            "nq_step_nvt", "nq_force_outliers",
            "nq_stats", "nq_ctx_graph_captures", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_ctx_set_variant", "nq_ctx_set_path", "nq_autotune", "nq_timing",
            "nq_timing_report",
@@ -87,6 +87,7 @@ def lib():
         "nq_energy_forces_replicas": (C.c_int, [vp, vp, vp, vp, i64, i64, P(dbl), vp, vp, vp]),
         "nq_energy_forces_domain": (C.c_int, [vp, vp, vp, vp, i64, i64, P(dbl), vp, vp, vp]),
         "nq_ring_polymer": (C.c_int, [vp, vp, vp, i64, i64, P(dbl), dbl, vp, vp]),
+        "nq_ring_polymer_noalloc": (C.c_int, [vp, vp, vp, i64, i64, P(dbl), dbl, vp, vp]),
         "nq_step": (C.c_int, [vp, vp, vp, vp, vp, vp, i64, P(dbl), dbl, i32, vp, vp, vp]),
         "nq_step_nvt": (C.c_int, [vp, vp, vp, vp, vp, vp, i64, P(dbl), dbl, i32, dbl, dbl, vp, vp, vp, vp, vp]),
         "nq_force_outliers": (C.c_int, [vp, vp, i64, dbl, vp]),

@@ -216,6 +216,7 @@ nq_status nq_ctx_create(int device, void* hip_stream, nq_ctx** out) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     NQ_HIP(hipDeviceGetAttribute(&c->num_cu, hipDeviceAttributeMultiprocessorCount, device));
+    c->rp_static = ring_polymer_static_scratch(device);
     *out = c;
   });
 }
@@ -346,19 +347,43 @@ nq_status nq_force_outliers(nq_ctx* ctx, const double* forces, int64_t n, double
   });
 }
 
+namespace {
+
+// Argument checks shared by both ring-polymer entry points; returns w_P (1/fs).
+double ring_polymer_check(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n, int64_t n_rep,
+                          const double cell[3], double temperature, double* forces, double* energy) {
+  NQ_REQUIRE(ctx && pos && inv_mass && cell && forces && energy, NQ_ERR_ARG, "null argument");
+  NQ_REQUIRE(n >= 1 && n_rep >= 1 && n * n_rep < ((int64_t)1 << 30), NQ_ERR_ARG, "n or n_rep out of range");
+  NQ_REQUIRE(std::isfinite(temperature) && temperature >= 0, NQ_ERR_ARG, "bad temperature");
+  for (int k = 0; k < 3; ++k) NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0, NQ_ERR_ARG, "bad cell");
+  // w_P = P k_B T / hbar (1/fs): k_B in eV/K, hbar in eV fs (CODATA 2018)
+  return (double)n_rep * 8.617333262e-5 * temperature / 0.6582119569;
+}
+
+}  // namespace
+
 nq_status nq_ring_polymer(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n, int64_t n_rep,
                           const double cell[3], double temperature, double* forces, double* energy) {
   return guarded(ctx, [&] {
-    NQ_REQUIRE(ctx && pos && inv_mass && cell && forces && energy, NQ_ERR_ARG, "null argument");
-    NQ_REQUIRE(n >= 1 && n_rep >= 1 && n * n_rep < ((int64_t)1 << 30), NQ_ERR_ARG, "n or n_rep out of range");
-    NQ_REQUIRE(std::isfinite(temperature) && temperature >= 0, NQ_ERR_ARG, "bad temperature");
-    for (int k = 0; k < 3; ++k) NQ_REQUIRE(std::isfinite(cell[k]) && cell[k] > 0, NQ_ERR_ARG, "bad cell");
+    const double omega_p = ring_polymer_check(ctx, pos, inv_mass, n, n_rep, cell, temperature, forces, energy);
     NQ_HIP(hipSetDevice(ctx->device));
-    // w_P = P k_B T / hbar (1/fs): k_B in eV/K, hbar in eV fs (CODATA 2018)
-    const double omega_p = (double)n_rep * 8.617333262e-5 * temperature / 0.6582119569;
     ctx->rp_scratch.ensure((size_t)(n * n_rep) * sizeof(double));
     ring_polymer_async(ctx->stream, pos, inv_mass, n, n_rep, omega_p, cell, forces, ctx->rp_scratch.as<double>(),
                        energy);
+    NQ_HIP(hipGetLastError());
+  });
+}
+
+nq_status nq_ring_polymer_noalloc(nq_ctx* ctx, const double* pos, const double* inv_mass, int64_t n,
+                                  int64_t n_rep, const double cell[3], double temperature, double* forces,
+                                  double* energy) {
+  return guarded(ctx, [&] {
+    const double omega_p = ring_polymer_check(ctx, pos, inv_mass, n, n_rep, cell, temperature, forces, energy);
+    NQ_REQUIRE(n * n_rep <= NQ_RING_POLYMER_NOALLOC_MAX, NQ_ERR_CAPACITY,
+               "n * n_rep exceeds the fixed ring-polymer array (NQ_RING_POLYMER_NOALLOC_MAX)");
+    NQ_REQUIRE(ctx->rp_static, NQ_ERR_DEVICE, "ring-polymer array not set up");
+    NQ_HIP(hipSetDevice(ctx->device));
+    ring_polymer_async(ctx->stream, pos, inv_mass, n, n_rep, omega_p, cell, forces, ctx->rp_static, energy);
     NQ_HIP(hipGetLastError());
   });
 }

@@ -3,6 +3,8 @@
 // Units: A, fs, amu, eV; 1 eV/(amu A) = 9.648533212e-3 A/fs^2 (CODATA 2018).
 #include "nq_internal.hpp"
 
+#include <mutex>
+
 namespace nq {
 
 namespace {
@@ -188,6 +190,30 @@ __global__ __launch_bounds__(1024) void k_sum(const double* __restrict__ v, int6
 }
 
 }  // namespace
+
+// Bond energies of nq_ring_polymer_noalloc. A fixed array in device memory:
+// every GPU the library runs on holds its own copy, at its own address, until
+// the process ends, and every call on that GPU shares it. In host code this
+// name is not a device address; kernels get the address that
+// ring_polymer_static_scratch() looked up.
+static __device__ __align__(256) double scratch[NQ_RING_POLYMER_NOALLOC_MAX];
+
+double* ring_polymer_static_scratch(int device) {
+  static std::mutex mu;
+  static std::vector<double*> addr;
+  std::lock_guard<std::mutex> lock(mu);
+  if ((size_t)device >= addr.size()) addr.resize((size_t)device + 1, nullptr);
+  if (!addr[(size_t)device]) {
+    int cur = -1;
+    NQ_HIP(hipGetDevice(&cur));
+    NQ_REQUIRE(cur == device, NQ_ERR_DEVICE, "ring-polymer scratch looked up with another device current");
+    void* p = nullptr;
+    NQ_HIP(hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)));
+    NQ_REQUIRE(p != nullptr, NQ_ERR_DEVICE, "no device address for the ring-polymer scratch");
+    addr[(size_t)device] = (double*)p;
+  }
+  return addr[(size_t)device];
+}
 
 void md_half_kick_async(hipStream_t s, double* vel, const double* forces, const double* inv_mass, int64_t n,
                         double half_dt) {

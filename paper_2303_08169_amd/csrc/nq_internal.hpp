@@ -202,6 +202,7 @@ struct nq_ctx {
   nq::DevBuf fz_scratch;  // per-workgroup scratch of the fused kernel
   int path = NQ_PATH_AUTO;  // nq_ctx_set_path
   nq::DevBuf rp_scratch;  // ring-polymer bond energies
+  double* rp_static = nullptr;  // this device's fixed bond-energy array (nq_ring_polymer_noalloc)
   int64_t last_edges = 0;
   int64_t ws_budget = (int64_t)160 << 30;  // bytes allowed for per-edge activations
   // per-launch timing with HIP events on the context's stream
@@ -268,6 +269,10 @@ void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass
                         double omega_p, const double box[3], double* forces, double* e_bond, double* energy);
 void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n,
                    double* out);
+// Device address of the fixed ring-polymer bond-energy array on `device`
+// (NQ_RING_POLYMER_NOALLOC_MAX doubles), looked up once per device; the
+// device must be current.
+double* ring_polymer_static_scratch(int device);
 
 // Start/stop a timed span on ctx->stream (no-ops unless timing is enabled).
 int span_begin(nq_ctx* ctx, const std::string& name, double flop_per_edge = 0, double byte_per_edge = 0,

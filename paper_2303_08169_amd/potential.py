@@ -129,9 +129,11 @@ class Potential:
                                                  _cell(box), _ptr(E), _ptr(F), _ptr(Ei)), self._ctx)
         return (E, F, Ei) if atom_energy else (E, F)
 
-    def ring_polymer(self, pos, inv_mass, box, temperature, forces, energy=None):
+    def ring_polymer(self, pos, inv_mass, box, temperature, forces, energy=None, noalloc=False):
         """Adds the ring-polymer spring forces of the beads pos [R, n, 3] to
-        forces [R, n, 3] and returns the spring energy [1] (eV)."""
+        forces [R, n, 3] and returns the spring energy [1] (eV). noalloc uses
+        the entry point that allocates no device memory (at most 2^20 beads x
+        atoms; pass `energy` too, so that nothing here allocates either)."""
         if pos.dim() != 3 or forces.shape != pos.shape or inv_mass.shape != (pos.shape[1],):
             raise ValueError("positions and forces [R, n, 3], inv_mass [n]")
         for t in (pos, inv_mass, forces):
@@ -139,8 +141,9 @@ class Potential:
                 raise TypeError("ring-polymer arrays must be contiguous float64 on the potential's device")
         E = energy if energy is not None else torch.empty(1, dtype=torch.float64, device=self.device)
         self._sync_stream()
-        B.check(self.lib.nq_ring_polymer(self._ctx, _ptr(pos), _ptr(inv_mass), pos.shape[1], pos.shape[0],
-                                         _cell(box), float(temperature), _ptr(forces), _ptr(E)), self._ctx)
+        fn = self.lib.nq_ring_polymer_noalloc if noalloc else self.lib.nq_ring_polymer
+        B.check(fn(self._ctx, _ptr(pos), _ptr(inv_mass), pos.shape[1], pos.shape[0], _cell(box), float(temperature),
+                   _ptr(forces), _ptr(E)), self._ctx)
         return E
 
     def step(self, pos, vel, inv_mass, species, box, dt_fs, n_steps, forces, epot=None, ekin=None):
