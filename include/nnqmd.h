@@ -286,8 +286,10 @@ nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes);
  * (tile shapes of the tiled kernel: rows per workgroup and wave grid; where
  * compiled for the product's shape, the two epilogue forms of the
  * weight-stationary kernel) over `reps` evaluations with HIP events on the
- * context's stream, and keeps the fastest for `model` (later calls, and MD
- * graphs captured later, use it). Positions/species/cell as in nq_energy_forces. If report is
+ * context's stream, and keeps the fastest for `model` (later calls use it;
+ * an MD graph captured before is captured again). Products run in the
+ * precision they have when it is called (nq_model_set_product_precision).
+ * Positions/species/cell as in nq_energy_forces. If report is
  * not NULL, a JSON object {"sites": [{"name", "np", "chosen", "ms": [...]}]} is
  * written to report[cap] (host); *len (host, may be NULL) receives its length.
  * Results of the energy/force evaluation do not depend on the choice.
@@ -295,6 +297,29 @@ nq_status nq_ctx_set_workspace_budget(nq_ctx* ctx, int64_t bytes);
 nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int32_t* species,
                       int64_t n, const double cell[3], int32_t reps, char* report, int64_t cap,
                       int64_t* len);
+
+/* Sets the kernel variant of one matrix-core product of `model`, as
+ * nq_autotune would: `site` is a product name from nq_autotune's report,
+ * `variant` >= 0 (taken modulo the product's variant count at launch). Lets a
+ * caller replay a recorded tuning in another process; results do not depend on
+ * it. Later evaluations use it (an MD graph captured before is captured
+ * again). A name that is not a product of the model has no effect. NQ_ERR_ARG
+ * for a null or empty name or a negative variant. Not thread-safe against
+ * concurrent evaluations. */
+nq_status nq_model_set_choice(nq_model* model, const char* site, int32_t variant);
+
+/* Arithmetic of one product of the layered path, overriding the model's
+ * precision for it: `site` is a matrix-core product name from nq_autotune's
+ * report ("fwd.latent1.0", "bwd.twobody.0", ...) or "tp_fwd<t>" / "tp_bwd<t>"
+ * for the channel mixing inside layer t's tensor product (forward / adjoint);
+ * `precision` is NQ_PRECISION_FP32, _BF16 or _BF16X3, or -1 to drop the
+ * override. Inputs and outputs of every product stay FP32 in memory, so any
+ * mixture is valid; the error of the result is what the mixture gives. A name
+ * that is not a product of the model has no effect. The fused path does not
+ * take overrides: with any set, NQ_PATH_FUSED evaluations return
+ * NQ_ERR_UNSUPPORTED. Later evaluations use it (an MD graph captured before is
+ * captured again). NQ_ERR_ARG for a null or empty name or another precision. */
+nq_status nq_model_set_product_precision(nq_model* model, const char* site, int32_t precision);
 
 /* Per-kernel timing. While enabled, every kernel launch of nq_energy_forces
  * (not of nq_step's graph) is bracketed by HIP events recorded on the

@@ -21,7 +21,7 @@ EXPORTS = ["nq_ctx_create", "nq_ctx_set_stream", "nq_ctx_destroy", "nq_model_wei
            "nq_model_create", "nq_model_destroy", "nq_neighbor_build", "nq_energy_forces",
            "nq_energy_forces_replicas", "nq_energy_forces_domain", "nq_ring_polymer", "nq_ring_polymer_noalloc", "nq_step",
            "nq_step_nvt", "nq_force_outliers",
-           "nq_stats", "nq_ctx_graph_captures", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_ctx_set_variant", "nq_ctx_set_path", "nq_autotune", "nq_timing",
+           "nq_stats", "nq_ctx_graph_captures", "nq_edges_export", "nq_debug_export", "nq_ctx_set_workspace_budget", "nq_ctx_set_variant", "nq_ctx_set_path", "nq_autotune", "nq_model_set_choice", "nq_model_set_product_precision", "nq_timing",
            "nq_timing_report",
            "nq_status_str", "nq_last_error"]
 
@@ -58,7 +58,9 @@ def make_desc(model, precision: str = "fp32") -> ModelDesc:
     d.r_cut = float(model.r_cut)
     d.avg_num_neighbors = float(model.avg_num_neighbors)
     d.energy_scale = float(model.energy_scale)
-    d.precision = PRECISION[precision]
+    # "mixed" is the split-BF16 model with some products overridden to plain
+    # BF16 after creation (Potential does that)
+    d.precision = PRECISION["bf16x3" if precision == "mixed" else precision]
     return d
 
 
@@ -98,6 +100,8 @@ def lib():
         "nq_ctx_set_workspace_budget": (C.c_int, [vp, i64]),
         "nq_ctx_set_variant": (C.c_int, [vp, C.c_int32]),
         "nq_ctx_set_path": (C.c_int, [vp, C.c_int32]),
+        "nq_model_set_choice": (C.c_int, [vp, C.c_char_p, C.c_int32]),
+        "nq_model_set_product_precision": (C.c_int, [vp, C.c_char_p, C.c_int32]),
         "nq_autotune": (C.c_int, [vp, vp, vp, vp, i64, P(dbl), i32, C.c_char_p, i64, P(i64)]),
         "nq_timing": (C.c_int, [vp, C.c_int]),
         "nq_timing_report": (C.c_int, [vp, C.c_char_p, i64, P(i64)]),

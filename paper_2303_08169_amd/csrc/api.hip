@@ -422,7 +422,8 @@ void md_run(nq_ctx* ctx, const nq_model* model, double* pos, double* vel, const 
                                   (const void*)(intptr_t)ctx->ws.cap, (const void*)(intptr_t)n_steps,
                                   (const void*)(intptr_t)ctx->ws.chunks.size(),
                                   ctx->ws.bufs.empty() ? nullptr : ctx->ws.bufs.front()->p,
-                                  ctx->md_scratch.p, (const void*)(intptr_t)ctx->gen};
+                                  ctx->md_scratch.p, (const void*)(intptr_t)ctx->gen,
+                                  (const void*)(intptr_t)model->version};
   auto push_double = [&](double v) {
     int64_t b;
     std::memcpy(&b, &v, sizeof(double));
@@ -596,6 +597,28 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
   });
 }
 
+nq_status nq_model_set_choice(nq_model* model, const char* site, int32_t variant) {
+  return guarded(nullptr, [&] {
+    NQ_REQUIRE(model && site && site[0] && variant >= 0, NQ_ERR_ARG, "bad product name or variant");
+    model->gemm_choice[site] = variant;
+    ++model->version;
+  });
+}
+
+nq_status nq_model_set_product_precision(nq_model* model, const char* site, int32_t precision) {
+  return guarded(nullptr, [&] {
+    NQ_REQUIRE(model && site && site[0], NQ_ERR_ARG, "null or empty product name");
+    NQ_REQUIRE(precision == -1 || precision == NQ_PRECISION_FP32 || precision == NQ_PRECISION_BF16 ||
+                   precision == NQ_PRECISION_BF16X3,
+               NQ_ERR_ARG, "bad precision");
+    if (precision < 0)
+      model->site_prec.erase(site);
+    else
+      model->site_prec[site] = precision;
+    ++model->version;
+  });
+}
+
 nq_status nq_ctx_set_variant(nq_ctx* ctx, int32_t variant) {
   return guarded(ctx, [&] {
     NQ_REQUIRE(ctx && variant >= NQ_VARIANT_LAST2, NQ_ERR_ARG, "bad kernel variant");
@@ -700,6 +723,7 @@ nq_status nq_autotune(nq_ctx* ctx, nq_model* model, const double* pos, const int
       for (int v = 1; v < nv && v < (int)kv.second.size(); ++v)
         if (kv.second[v] < kv.second[best]) best = v;
       model->gemm_choice[kv.first] = best;
+      ++model->version;
       out += std::string(first ? "" : ", ") + "{\"name\": \"" + kv.first + "\", \"np\": " + std::to_string(np) +
              ", \"chosen\": " + std::to_string(best) + ", \"ms\": [";
       for (int v = 0; v < nv && v < (int)kv.second.size(); ++v)

@@ -1115,12 +1115,14 @@ __global__ __launch_bounds__(NTH) void k_fused(Args ka) {
 
 }  // namespace fz
 
-// True when the fused kernel is compiled for this model.
+// True when the fused kernel is compiled for this model (one precision for
+// every product: no per-product overrides).
 bool fused_supported(const nq_model* m) {
   const Dims& d = m->dims;
   return d.L == 2 && d.T == 2 && d.C == 32 && d.S == 3 && d.nb == 8 && d.n_tb == 3 && d.tb[0] == fz::TB0 &&
          d.tb[1] == fz::TB1 && d.tb[2] == fz::D && d.n_lat == 1 && d.lat[0] == fz::D && d.n_edge == 1 &&
-         d.edge[0] == fz::EDGE && (d.prec == NQ_PRECISION_BF16 || d.prec == NQ_PRECISION_BF16X3);
+         d.edge[0] == fz::EDGE && (d.prec == NQ_PRECISION_BF16 || d.prec == NQ_PRECISION_BF16X3) &&
+         m->site_prec.empty();
 }
 
 namespace {

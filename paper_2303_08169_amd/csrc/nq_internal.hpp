@@ -117,6 +117,8 @@ struct nq_model {
   std::vector<double> tp_flop_fwd, tp_flop_bwd;  // algorithmic FLOPs per edge of each layer's tensor product
   std::vector<double> tp_flop_mix;               // ... of which the channel mixing (matrix cores), each direction
   mutable std::map<std::string, int> gemm_choice;  // tuned tile shape per matrix-core product
+  std::map<std::string, int> site_prec;            // per-product precision (nq_model_set_product_precision)
+  int64_t version = 0;  // bumped when a kernel choice or precision changes (part of the MD graph key)
   ~nq_model();
 };
 
@@ -273,6 +275,12 @@ void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int
 // (NQ_RING_POLYMER_NOALLOC_MAX doubles), looked up once per device; the
 // device must be current.
 double* ring_polymer_static_scratch(int device);
+
+// Arithmetic of one product site: its override, else the model's precision.
+inline int site_precision(const nq_model* m, const std::string& site) {
+  auto it = m->site_prec.find(site);
+  return it == m->site_prec.end() ? m->dims.prec : it->second;
+}
 
 // Start/stop a timed span on ctx->stream (no-ops unless timing is enabled).
 int span_begin(nq_ctx* ctx, const std::string& name, double flop_per_edge = 0, double byte_per_edge = 0,

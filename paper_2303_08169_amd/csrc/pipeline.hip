@@ -1276,8 +1276,8 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
     auto it = m->gemm_choice.find(name);
     if (it != m->gemm_choice.end()) v = it->second;
   }
-  const int kind = m->dims.prec == NQ_PRECISION_BF16X3 ? G_BF16X3
-                   : (m->dims.prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32);
+  const int prec = site_precision(m, name);
+  const int kind = prec == NQ_PRECISION_BF16X3 ? G_BF16X3 : (prec == NQ_PRECISION_BF16 ? G_BF16 : G_F32);
   const void* Bbf = (bwd ? L.bf_bwd : L.bf_fwd).p;
   const int ntile = gemm_variants(kind, NP);
   const bool has_ws = gemm_ws(false, 0, kind, ctx->stream, ctx->num_cu, NP, Kp, Bbf, nr, ld, ep);
@@ -1294,7 +1294,7 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
     span_end(ctx, sp);
     return;
   }
-  switch (m->dims.prec) {
+  switch (prec) {
     case NQ_PRECISION_BF16:
       launch_gemm_np<G_BF16>(ctx->stream, ws.cap, NP, Kp, Bbf, nr, ld, ep, v);
       break;
@@ -1388,7 +1388,7 @@ void launch_tp_fwd(nq_ctx* ctx, const nq_model* m, int t) {
     k_tp_fwd_last32<K><<<tp_grid(ctx, k_tp_fwd_last32<K>, 0, d.C), 256, 0, ctx->stream>>>(a);     \
   else                                                                                            \
     k_tp_fwd<K, LM, false><<<tp_grid(ctx, k_tp_fwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
-  switch (d.prec * 2 + (d.L == 2)) {
+  switch (site_precision(m, "tp_fwd" + std::to_string(t)) * 2 + (d.L == 2)) {
     case 0: NQ_TPF(G_F32, 1); break;
     case 1: NQ_TPF(G_F32, 2); break;
     case 2: NQ_TPF(G_BF16, 1); break;
@@ -1426,7 +1426,7 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
     k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, 0, d.C), 256, 0, ctx->stream>>>(a);     \
   else                                                                                            \
     k_tp_bwd<K, LM, false><<<tp_grid(ctx, k_tp_bwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
-  switch (d.prec * 2 + (d.L == 2)) {
+  switch (site_precision(m, "tp_bwd" + std::to_string(t)) * 2 + (d.L == 2)) {
     case 0: NQ_TPB(G_F32, 1); break;
     case 1: NQ_TPB(G_F32, 2); break;
     case 2: NQ_TPB(G_BF16, 1); break;

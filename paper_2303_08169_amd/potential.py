@@ -25,6 +25,18 @@ def _cell(box):
     return (C.c_double * 3)(*b.tolist())
 
 
+# Products of the split-BF16 model that run in plain BF16 in the "mixed"
+# precision: the channel mixing of the tensor product (both directions), the
+# environment embeddings of the second layer and the adjoint of the first
+# layer's tensor-feature/environment embedding. Chosen by a per-product study
+# on the 1,024-atom system against the FP64 oracle (bench.py --sensitivity):
+# each alone in plain BF16 moves the force error by less than 1e-4 relative
+# and the energy error by less than 3e-6, and all together keep both below
+# half the 1e-3 / 1e-5 targets. The two-body, latent and edge-energy MLPs stay
+# split (each alone in plain BF16 moves the force error by 5e-4 to 5e-3).
+MIXED_BF16 = ("bwd.env2", "tp_bwd1", "tp_fwd1", "fwd.env2", "bwd.v0env1")
+
+
 class Potential:
     """One context + one model on a GPU.
 
@@ -53,6 +65,8 @@ class Potential:
                                              w.ctypes.data_as(C.POINTER(C.c_double)), w.size,
                                              C.byref(self._model)), self._ctx)
         self._energy = torch.zeros(1, dtype=torch.float64, device=self.device)
+        if precision == "mixed":
+            self.set_product_precision({site: "bf16" for site in MIXED_BF16})
 
     def close(self):
         if getattr(self, "_model", None):
@@ -184,6 +198,21 @@ class Potential:
         B.check(self.lib.nq_autotune(self._ctx, self._model, _ptr(pos), _ptr(species), pos.shape[0], _cell(box),
                                      int(reps), buf, len(buf), C.byref(n)), self._ctx)
         return json.loads(buf.value.decode())
+
+    def set_choice(self, choices):
+        """Kernel variant per matrix-core product ({name: variant}, as in the
+        "chosen" entries of autotune()'s report), e.g. replayed from a file."""
+        for name, v in choices.items():
+            B.check(self.lib.nq_model_set_choice(self._model, name.encode(), int(v)), self._ctx)
+
+    def set_product_precision(self, precisions):
+        """Arithmetic per product ({site: "fp32" | "bf16" | "bf16x3" | None}),
+        overriding the model's precision; sites are the matrix-core product
+        names of autotune()'s report and "tp_fwd<t>" / "tp_bwd<t>" (channel
+        mixing of layer t). None drops an override."""
+        for name, p in precisions.items():
+            v = -1 if p is None else B.PRECISION[p]
+            B.check(self.lib.nq_model_set_product_precision(self._model, name.encode(), v), self._ctx)
 
     def set_variant(self, variant: int):
         """Kernel choice of the matrix-core products: -1 tuned (default), -2 / -3
