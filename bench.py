@@ -200,7 +200,7 @@ def roofline(report, steps, precision, path, workload, n_atoms, n_edges, n_weigh
     out = {"bound": "mfma", "achieved": mfma / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s"}
     out["frac"] = out["achieved"] / peak
     rec = recorded_counters(precision, path, workload)
-    kc = rec["spans"].get(dom["name"]) if rec else None
+    kc = rec.get("spans", {}).get(dom["name"]) if rec else None
     out["traffic"] = kc["hbm_bytes_per_launch"] if kc else None
     out["kernel"] = dom["name"]
     out["avg_launch_ms"] = avg_s * 1e3

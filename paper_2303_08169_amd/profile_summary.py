@@ -145,6 +145,29 @@ def per_span(path, spans, evals):
     return out, dict(total)
 
 
+def per_kernel(path, spans, evals):
+    """Like per_span, keyed by the library kernel's name (for evaluations that
+    run some spans several times, e.g. in centre chunks): (kernel, counters
+    per evaluation, ns per evaluation, launches per evaluation)."""
+    groups = evaluations(read_dispatches(path), spans, evals)
+    out = {}
+    for g in groups:
+        for name, ctr, dur in g:
+            b = base_name(name)
+            names, tot, ns, cnt = out.setdefault(b, ([b], collections.defaultdict(float), [0.0], [0]))
+            for k, v in ctr.items():
+                tot[k] += v / evals
+            if dur is not None:
+                ns[0] += dur / evals
+            cnt[0] += 1
+    res = {b: (names, dict(tot), ns[0], cnt[0] / evals) for b, (names, tot, ns, cnt) in out.items()}
+    total = collections.defaultdict(float)
+    for _, tot, _, _ in res.values():
+        for k, v in tot.items():
+            total[k] += v
+    return res, dict(total)
+
+
 def copy_scale(path, counter, nbytes):
     """nbytes / (KiB the counter reads for the largest plain device copy)."""
     best = 0.0
@@ -175,25 +198,37 @@ def main(argv=None):
 
     prof = json.load(open(a.spans))
     spans, evals = prof["spans"], prof["evals"]
-    if any(c != evals for c in prof["span_counts"]):
-        raise SystemExit("every span must run once per evaluation (no centre chunks)")
+    # spans that run once per evaluation are named after the spans; otherwise
+    # (centre chunks) the figures are per kernel
+    by_span = all(c == evals for c in prof["span_counts"])
+
+    def collect(path):
+        if by_span:
+            res, tot = per_span(path, spans, evals)
+            return {k: (v[0], v[1], v[2], 1.0) for k, v in res.items()}, tot
+        return per_kernel(path, spans, evals)
+
     rec = {"workload": prof["workload"], "precision": prof["precision"], "path": prof["path"],
-           "edges": prof["edges"], "evals": evals, "source_sha256": prof["source_sha256"], "spans": {}}
-    rows = {s: {"kernels": None} for s in spans}
+           "edges": prof["edges"], "evals": evals, "source_sha256": prof["source_sha256"],
+           "keyed_by": "span" if by_span else "kernel"}
+    rows = collections.OrderedDict((s, {"kernels": None}) for s in spans) if by_span else collections.OrderedDict()
     if a.trace:
-        ts, _ = per_span(a.trace, spans, evals)
-        for s, (names, _, ns, _) in ts.items():
-            rows[s].update(kernels=names, avg_ms_trace=ns * 1e-6)
+        ts, _ = collect(a.trace)
+        for s, (names, _, ns, per) in ts.items():
+            rows.setdefault(s, {}).update(kernels=names, avg_ms_trace=ns * 1e-6 / per, launches_per_eval=per,
+                                          ms_per_eval=ns * 1e-6)
     if a.fetch and a.write:
         fs = copy_scale(a.copy_fetch, "FETCH_SIZE", a.copy_bytes)
         ws = copy_scale(a.copy_write, "WRITE_SIZE", a.copy_bytes)
         rec.update(fetch_scale=fs, write_scale=ws)
-        f, ftot = per_span(a.fetch, spans, evals)
-        w, wtot = per_span(a.write, spans, evals)
-        for s in spans:
-            fk, wk = f[s][1].get("FETCH_SIZE", 0.0), w[s][1].get("WRITE_SIZE", 0.0)
-            rows[s].update(fetch_kib=fk, write_kib=wk, hbm_bytes_per_launch=1024.0 * (fk * fs + wk * ws),
-                           kernels=rows[s]["kernels"] or f[s][0], rocprof_names=f[s][3])
+        f, ftot = collect(a.fetch)
+        w, wtot = collect(a.write)
+        for s in f:
+            fk, wk = f[s][1].get("FETCH_SIZE", 0.0), w.get(s, f[s])[1].get("WRITE_SIZE", 0.0)
+            per = f[s][3]
+            rows.setdefault(s, {}).update(fetch_kib=fk / per, write_kib=wk / per,
+                                          hbm_bytes_per_launch=1024.0 * (fk * fs + wk * ws) / per,
+                                          kernels=rows.get(s, {}).get("kernels") or f[s][0])
         rec["hbm_bytes_per_step"] = 1024.0 * (ftot.get("FETCH_SIZE", 0.0) * fs + wtot.get("WRITE_SIZE", 0.0) * ws)
     agent = {}
     if a.agent:
@@ -202,11 +237,10 @@ def main(argv=None):
                 agent = {k: int(r[k]) for k in ("Simd_Count", "Cu_Count", "Num_Xcc")}
         rec["agent"] = agent
     for path in a.sq:
-        q, _ = per_span(path, spans, evals)
-        for s in spans:
-            c = q[s][1]
-            rows[s].setdefault("sq", {}).update(c)
-    for s in spans:
+        q, _ = collect(path)
+        for s in q:
+            rows.setdefault(s, {}).setdefault("sq", {}).update(q[s][1])
+    for s in rows:
         c = rows[s].get("sq")
         if not c or "GRBM_GUI_ACTIVE" not in c or not agent:
             continue
@@ -222,10 +256,10 @@ def main(argv=None):
             d["lds_bank_conflict_per_lds_inst"] = c["SQ_LDS_BANK_CONFLICT"] / c["SQ_INSTS_LDS"]
         if "SQ_INSTS_VALU_MFMA_MOPS_BF16" in c:
             d["mfma_bf16_flop_counted"] = 512.0 * c["SQ_INSTS_VALU_MFMA_MOPS_BF16"]
-        if rows[s].get("avg_ms_trace"):
-            d["clock_ghz_implied"] = cyc / (rows[s]["avg_ms_trace"] * 1e6)
+        if rows[s].get("ms_per_eval"):
+            d["clock_ghz_implied"] = cyc / (rows[s]["ms_per_eval"] * 1e6)
         rows[s].update(d)
-    rec["spans"] = rows
+    rec["spans" if by_span else "kernels"] = rows
     rec["source_file"] = a.md.split("/")[-1]
     with open(a.json, "w") as fh:
         json.dump(rec, fh, indent=1)
@@ -241,18 +275,22 @@ def main(argv=None):
                 f"the factors make a plain device copy of {a.copy_bytes / 2**20:,.0f} MiB read and write exactly that "
                 "many bytes.", "",
                 f"HBM bytes per evaluation (all kernels): {rec['hbm_bytes_per_step'] / 1e9:.2f} GB.", ""]
-    hdr = ["span", "kernels", "avg ms (trace)", "HBM GB/launch", "MFMA busy", "VALU busy", "issue wait",
+    if not by_span:
+        out += ["Centre chunks run some spans several times per evaluation, so the rows are the library's "
+                "kernels (all their launches in one evaluation).", ""]
+    hdr = ["span" if by_span else "kernel", "kernels", "launches", "avg ms (trace)", "HBM GB/launch", "MFMA busy", "VALU busy", "issue wait",
            "LDS conflicts/inst", "clock GHz"]
     out += ["| " + " | ".join(hdr) + " |", "|" + "---|" * len(hdr)]
 
     def f_(v, fmt):
         return "-" if v is None else format(v, fmt)
 
-    for s in sorted(spans, key=lambda s: -(rows[s].get("avg_ms_trace") or 0)):
+    for s in sorted(rows, key=lambda s: -(rows[s].get("ms_per_eval") or 0)):
         r = rows[s]
         hb = r.get("hbm_bytes_per_launch")
         out.append("| " + " | ".join([
-            s, ", ".join(r.get("kernels") or []), f_(r.get("avg_ms_trace"), ".3f"),
+            s, ", ".join(r.get("kernels") or []), f_(r.get("launches_per_eval"), ".0f"),
+            f_(r.get("avg_ms_trace"), ".3f"),
             f_(hb / 1e9 if hb is not None else None, ".3f"), f_(r.get("mfma_busy"), ".3f"),
             f_(r.get("valu_busy"), ".3f"), f_(r.get("wait_any"), ".3f"),
             f_(r.get("lds_bank_conflict_per_lds_inst"), ".3f"), f_(r.get("clock_ghz_implied"), ".2f")]) + " |")

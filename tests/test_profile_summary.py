@@ -123,3 +123,24 @@ def test_missing_marker_or_wrong_count_is_an_error(tmp_path):
     with pytest.raises(ValueError, match="expected 4"):
         ps.main(["--spans", str(spans), "--trace", str(tmp_path / "trace.csv"), "--json", str(tmp_path / "x.json"),
                  "--md", str(tmp_path / "x.md")])
+
+
+def test_chunked_evaluations_are_keyed_by_kernel(tmp_path):
+    spans = _setup(tmp_path, evals=3)
+    d = json.loads(spans.read_text())
+    d["span_counts"][3] = 6    # a span that runs twice per evaluation (two centre chunks)
+    spans.write_text(json.dumps(d))
+    out = tmp_path / "k.json"
+    ps.main(["--spans", str(spans), "--trace", str(tmp_path / "trace.csv"), "--fetch", str(tmp_path / "fetch.csv"),
+             "--write", str(tmp_path / "write.csv"), "--copy-fetch", str(tmp_path / "cf.csv"),
+             "--copy-write", str(tmp_path / "cw.csv"), "--copy-bytes", str(1 << 20),
+             "--json", str(out), "--md", str(tmp_path / "k.md")])
+    rec = json.loads(out.read_text())
+    assert rec["keyed_by"] == "kernel" and "spans" not in rec
+    k = rec["kernels"]
+    assert set(k) == {"k_displacement", "k_edge_count", "k_scan_block", "k_geometry", "k_gemm_ws", "k_tp_fwd",
+                      "k_forces", "k_total_energy"}
+    assert k["k_gemm_ws"]["launches_per_eval"] == 1 and k["k_gemm_ws"]["avg_ms_trace"] == pytest.approx(0.05)
+    assert k["k_gemm_ws"]["hbm_bytes_per_launch"] == pytest.approx(1024 * (50 * 2 + 100))
+    per_eval = sum(v for _, v in EVAL)
+    assert rec["hbm_bytes_per_step"] == pytest.approx(1024 * (per_eval * 2 + 2 * per_eval))
