@@ -188,19 +188,38 @@ def roofline(report, steps, precision, path, workload, n_atoms, n_edges, n_weigh
     split products, the vector-ALU fraction of the kernel's non-matrix FLOPs,
     the HBM fraction of its counter bytes, and the step as a whole against the
     matrix-core floor of the method's FLOPs."""
+    import re
+
     ks = report["kernels"]
-    dom = max(ks, key=lambda k: k["ms_total"])
+    # launches of one kernel on the same shape in different layers count as
+    # one kernel (the latent products of layers 1 and 2 run the same code on
+    # the same sizes)
+    groups = {}
+    for k in ks:
+        key = (re.sub(r"\d+", "#", k["name"]), round(k["flop_per_launch"]), round(k["bytes_per_launch"]))
+        g = groups.setdefault(key, {"names": [], "ms_total": 0.0, "count": 0, "flop_per_launch": k["flop_per_launch"],
+                                    "mfma_flop_per_launch": k.get("mfma_flop_per_launch", 0.0)})
+        g["names"].append(k["name"])
+        g["ms_total"] += k["ms_total"]
+        g["count"] += k["count"]
+    dom = max(groups.values(), key=lambda g: g["ms_total"])
+    dom["name"] = "+".join(dom["names"])
     avg_s = dom["ms_total"] / dom["count"] * 1e-3
-    mfma = dom.get("mfma_flop_per_launch", 0.0)
+    mfma = dom["mfma_flop_per_launch"]
     valu = dom["flop_per_launch"] - mfma
     cdt = "fp32" if precision == "fp32" else "bf16"
     peak = MFMA_PEAK_TFLOPS[cdt]
     from paper_2303_08169_amd.potential import MIXED_BF16
-    passes = 3 if precision == "bf16x3" or (precision == "mixed" and dom["name"] not in MIXED_BF16) else 1
+    passes = 3 if precision == "bf16x3" or (precision == "mixed" and dom["names"][0] not in MIXED_BF16) else 1
     out = {"bound": "mfma", "achieved": mfma / avg_s / 1e12, "peak": peak, "unit": "TFLOP/s"}
     out["frac"] = out["achieved"] / peak
     rec = recorded_counters(precision, path, workload)
-    kc = rec.get("spans", {}).get(dom["name"]) if rec else None
+    members = [rec.get("spans", {}).get(n) for n in dom["names"]] if rec else [None]
+    kc = None
+    if all(m and "hbm_bytes_per_launch" in m for m in members):
+        kc = {f: sum(m[f] for m in members) / len(members)
+              for f in ("hbm_bytes_per_launch", "avg_ms_trace", "mfma_busy", "valu_busy", "wait_any",
+                        "lds_bank_conflict_per_lds_inst") if all(f in m for m in members)}
     out["traffic"] = kc["hbm_bytes_per_launch"] if kc else None
     out["kernel"] = dom["name"]
     out["avg_launch_ms"] = avg_s * 1e3
@@ -214,9 +233,9 @@ def roofline(report, steps, precision, path, workload, n_atoms, n_edges, n_weigh
         "hbm_counters": (kc["hbm_bytes_per_launch"] / avg_s / 1e9 / HBM_GBS) if kc else None,
     }
     if kc:
-        out["counters"] = {k: kc[k] for k in ("mfma_busy", "valu_busy", "wait_any", "lds_bank_conflict_per_lds_inst")
-                           if k in kc}
-        out["counters_source"] = rec["source_file"]
+        out["counters"] = {k: kc[k] for k in ("mfma_busy", "valu_busy", "wait_any", "lds_bank_conflict_per_lds_inst",
+                                              "avg_ms_trace") if k in kc}
+        out["counters_source"] = "profiles/" + rec["source_file"]
     flop_edge = 4.0 * method_mac_per_edge(model)
     step_flop = flop_edge * n_edges
     alg = algorithmic_bytes(n_atoms, n_edges, n_weights, precision)

@@ -259,6 +259,8 @@ def main(argv=None):
         if rows[s].get("ms_per_eval"):
             d["clock_ghz_implied"] = cyc / (rows[s]["ms_per_eval"] * 1e6)
         rows[s].update(d)
+    for r in rows.values():
+        r.pop("sq", None)  # raw counter sums: only the fractions above are kept
     rec["spans" if by_span else "kernels"] = rows
     rec["source_file"] = a.md.split("/")[-1]
     with open(a.json, "w") as fh:
