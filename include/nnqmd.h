@@ -327,8 +327,10 @@ nq_status nq_model_set_product_precision(nq_model* model, const char* site, int3
  * object {"n_edges": E, "kernels": [{"name", "count", "ms_total",
  * "flop_per_launch", "mfma_flop_per_launch", "bytes_per_launch"}...]}
  * (algorithmic FLOPs, the part of them done on the matrix cores, and HBM bytes
- * of one launch at the last edge count) into buf[cap] (host), then clears the
- * record. *len (host) receives the length; NQ_ERR_CAPACITY if buf is too
+ * of one launch at the last edge count, averaged over the launches: a kernel
+ * that runs once per chunk of centres gets its share of the edges) into
+ * buf[cap] (host), then clears the record. The record should cover whole
+ * evaluations of one system. *len (host) receives the length; NQ_ERR_CAPACITY if buf is too
  * small. */
 nq_status nq_timing(nq_ctx* ctx, int enable);
 nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len);

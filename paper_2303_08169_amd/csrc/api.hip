@@ -770,6 +770,8 @@ nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
       }
       agg[k].count++;
       agg[k].ms += ms;
+      // per evaluation: a span inside the centre-chunk loop runs once per
+      // chunk and its launches together cover every edge once
       agg[k].flop = s.flop_per_edge * ne + s.flop_per_atom * (double)ctx->ws.n_atoms;
       agg[k].byte = s.byte_per_edge * ne + s.byte_per_atom * (double)ctx->ws.n_atoms;
       agg[k].mfma = s.mfma_flop_per_edge * ne;
@@ -777,6 +779,18 @@ nq_status nq_timing_report(nq_ctx* ctx, char* buf, int64_t cap, int64_t* len) {
       ctx->event_pool.push_back(s.b);
     }
     ctx->spans.clear();
+    // evaluations covered: the launches of the once-per-evaluation energy sum
+    int n_eval = 0;
+    for (size_t k = 0; k < order.size(); ++k)
+      if (order[k] == "total_energy") n_eval = agg[k].count;
+    if (n_eval == 0)
+      for (const Agg& g : agg) n_eval = n_eval ? std::min(n_eval, g.count) : g.count;
+    for (Agg& g : agg) {
+      const double per = (double)n_eval / (double)g.count;  // evaluations per launch
+      g.flop *= per;
+      g.byte *= per;
+      g.mfma *= per;
+    }
     std::string out = "{\"n_edges\": " + std::to_string(ne) + ", \"kernels\": [";
     char tmp[512];
     for (size_t k = 0; k < order.size(); ++k) {

@@ -490,7 +490,14 @@ static_assert(Paths<2>::pi.toff[0][0] == mix32::TOFF[0][0] && Paths<2>::pi.toff[
 // group's (256 / C) edges x (NT, plus NY for the adjoint) components.
 inline size_t tp_lds_bytes(int C, int L, bool adjoint) {
   const int NT = L == 1 ? 8 : 35, NY = (L + 1) * (L + 1);
-  return (size_t)(256 / C) * (C + 4) * (NT + (adjoint ? NY : 0)) * sizeof(float);
+  // the adjoint adds two buffers of the group's edge centres (run sums)
+  return (size_t)(256 / C) * ((C + 4) * (NT + (adjoint ? NY : 0)) + (adjoint ? 2 : 0)) * sizeof(float);
+}
+// Dynamic LDS of the last layer's 32-channel adjoint: two alternating buffers
+// of the group's dE/dGamma contributions and of its edge centres.
+inline size_t tp_last_lds_bytes(int C, int L) {
+  const int NY = (L + 1) * (L + 1);
+  return (size_t)(256 / C) * (2 * NY * (C + 4) + 2) * sizeof(float);
 }
 
 struct TpFwdArgs {
@@ -715,6 +722,7 @@ __global__ void k_fill(float* __restrict__ p, int64_t n, float v) {
 
 struct TpBwdArgs {
   const int* nedge_p;
+  const int* e0p;  // global index of edge 0 (the chunk's first edge)
   const int* ei;
   const float* geo;
   int C, first, last;
@@ -733,6 +741,10 @@ struct TpBwdArgs {
   float* gY;
   int ldgy;
 };
+
+// Workgroup barrier that waits for this wavefront's LDS accesses only: global
+// loads in flight (the next group's inputs) stay in flight across it.
+__device__ inline void tp_lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
 
 // Inputs of the adjoint of one (edge, channel) that do not depend on the
 // mixing adjoint: V_{t-1}, Gamma_i and dE/ds. They are loaded before the
@@ -758,15 +770,17 @@ __device__ inline void tp_bwd_load(const TpBwdArgs& a, int64_t e, int ctr, int c
 
 // Adjoint of the tensor product of one (edge, channel), given dE/dT from the
 // mixing adjoint (gTrow: this edge's rows in LDS, unused for the last layer)
-// and dE/ds. Writes the per-edge contributions ggc[e][lm][c] to dE/dGamma_i,
-// and either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
+// and dE/ds. Writes the edge's contributions to dE/dGamma_i into LDS
+// (red[lm * CP + c]: only this thread reads or writes these words before the
+// next barrier; the caller sums them over the runs of equal centres), and
+// either dE/dV_{t-1} (t > 1) or, for t = 1, dE/dw0 into gew[:, 0:NW] and
 // the w0 part of dE/dY into slot 0 of the edge's dE/dY row (a plain store:
 // the geometry adjoint adds the slots, and a read-modify-write here would wait
 // on every outstanding load of the next group). CC: channel count if known at
 // compile time.
 template <int LMAX, int CC>
-__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int nval, int el, int c, const float* gTrow,
-                                   int CP, const TpBwdIn<LMAX>& in) {
+__device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int lo, int hi, int el, int c,
+                                   const float* gTrow, int CP, const TpBwdIn<LMAX>& in, float* red) {
   constexpr int NY = TPSize<LMAX>::NY;
   const int C = CC > 0 ? CC : a.C;
   float gV[NY], gG[NY], V[NY];
@@ -798,9 +812,8 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int nval, int
     // 32-channel plan (called for valid rows only): plain stores, which keep
     // its register peak lower than buffer offsets do
     const int64_t e = e0 + el;
-    float* ggr = a.ggc + e * (NY * C) + c;
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = gG[lm];
+    for (int lm = 0; lm < NY; ++lm) red[lm * CP + c] = gG[lm];
     if (!a.first) {
       float* gvr = a.gvout + e * (NY * C) + c;
 #pragma unroll
@@ -823,22 +836,25 @@ __device__ inline void tp_bwd_edge(const TpBwdArgs& a, int64_t e0, int nval, int
       }
     }
   } else {
-    // stores through buffers over the group's nval valid rows (edge el of
-    // the group; a row past the last edge is dropped), so no branch guards them
-    const unsigned rowc = (unsigned)(el * NY * C + c) * 4;
-    const __amdgpu_buffer_rsrc_t GG = buffer_rsrc(a.ggc + e0 * (NY * C), (int64_t)nval * NY * C * 4);
+    // stores through buffers over the group's valid rows lo .. hi - 1 (edge
+    // e0 + el; a row outside them is dropped: its offset, negative before lo,
+    // wraps past the range), so no branch guards them
+    const int r = el - lo;
+    const int64_t eb = e0 + lo;
+    const int nval = hi - lo;
+    const unsigned rowc = (unsigned)((r * NY * C + c) * 4);
 #pragma unroll
-    for (int lm = 0; lm < NY; ++lm) buf_store(gG[lm], GG, rowc + (unsigned)(lm * C) * 4);
+    for (int lm = 0; lm < NY; ++lm) red[lm * CP + c] = gG[lm];
     if (!a.first) {
-      const __amdgpu_buffer_rsrc_t GV = buffer_rsrc(a.gvout + e0 * (NY * C), (int64_t)nval * NY * C * 4);
+      const __amdgpu_buffer_rsrc_t GV = buffer_rsrc(a.gvout + eb * (NY * C), (int64_t)nval * NY * C * 4);
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) buf_store(gV[lm], GV, rowc + (unsigned)(lm * C) * 4);
     } else {
       // V0[c][lm] = w0[l][c] Y[lm]; each component's channel sum is reduced
       // right away (gathering them first raises the register peak)
-      const __amdgpu_buffer_rsrc_t GW = buffer_rsrc(a.gew + e0 * a.ldgew, (int64_t)nval * a.ldgew * 4);
-      const __amdgpu_buffer_rsrc_t GY = buffer_rsrc(a.gY + e0 * a.ldgy, (int64_t)nval * a.ldgy * 4);
-      const unsigned gwo = (unsigned)(el * a.ldgew + c) * 4, gyo = (unsigned)(el * a.ldgy) * 4;
+      const __amdgpu_buffer_rsrc_t GW = buffer_rsrc(a.gew + eb * a.ldgew, (int64_t)nval * a.ldgew * 4);
+      const __amdgpu_buffer_rsrc_t GY = buffer_rsrc(a.gY + eb * a.ldgy, (int64_t)nval * a.ldgy * 4);
+      const unsigned gwo = (unsigned)((r * a.ldgew + c) * 4), gyo = (unsigned)(r * a.ldgy * 4);
 #pragma unroll
       for (int l = 0; l <= LMAX; ++l) {
         float gw = 0.f;
@@ -871,7 +887,11 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   float* gVl = nq_dyn_lds;
   float* gTl = nq_dyn_lds + epb * NY * CP;
   const int64_t ne = *a.nedge_p;
-  const int64_t ngroups = (ne + epb - 1) / epb;
+  // groups of epb edges start at multiples of epb of the global edge index
+  // (edge e of a chunk is edge e0 + e of the system), so the run sums below
+  // do not depend on how the centres are split into chunks
+  const int sh = __builtin_amdgcn_readfirstlane(*a.e0p % epb);
+  const int64_t ngroups = ne > 0 ? (ne + sh + epb - 1) / epb : 0;
   mix32::BwdB<KIND, (MW < 0 ? 0 : MW)> B;
   if constexpr (MW >= 0) {
     if (!a.last) B.load(KIND == G_F32 ? static_cast<const void*>(a.W.fN) : a.W.bN, a.W.n, lane);
@@ -884,8 +904,8 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   TpBwdIn<LMAX> in;
   // The centre index of a group is loaded one group earlier still.
   auto edge_of = [&](int64_t g) {
-    const int64_t eg = g * epb + el;
-    return eg < ne ? eg : ne - 1;
+    const int64_t eg = g * epb + el - sh;
+    return eg < 0 ? 0 : (eg < ne ? eg : ne - 1);
   };
   auto clampg = [&](int64_t g) { return g < ngroups ? g : ngroups - 1; };
   auto issue = [&](int64_t g, int ctr, float (&gvr)[NY], TpBwdIn<LMAX>& inr) {
@@ -897,15 +917,33 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     }
     tp_bwd_load<LMAX, CC>(a, ec, ctr, c, inr);
   };
+  // dE/dGamma: the group's edges put their contributions into LDS and the
+  // first edge of every run of equal centres within the group stores the
+  // run's sum (in edge order) at its row of ggc; no other row is written:
+  // rows are written at each centre's first edge and at every global
+  // multiple of epb inside its edges.
+  // With mixing the rows go into the edge's own dE/dT rows (read only by the
+  // same thread, and rewritten by the next group's mixing only after the next
+  // staging barrier); without, into two alternating buffers.
+  const bool mixing = !LAST && !a.last;
+  float* const redbase = mixing ? gTl : nq_dyn_lds;
+  const int rstride = mixing ? NT * CP : NY * CP;
+  int* const centbase = reinterpret_cast<int*>(mixing ? gTl + epb * NT * CP : nq_dyn_lds + 2 * epb * NY * CP);
   int64_t grp = blockIdx.x;
-  int ctr = 0;
+  int ctr = 0, cur = 0;
   if (grp < ngroups) {
-    issue(grp, a.ei[edge_of(grp)], gv, in);
+    cur = a.ei[edge_of(grp)];
+    issue(grp, cur, gv, in);
     ctr = a.ei[edge_of(clampg(grp + gridDim.x))];
   }
-  for (; grp < ngroups; grp += gridDim.x) {
-    const int64_t e = grp * epb + el;
-    const bool valid = e < ne;
+  for (int it = 0; grp < ngroups; grp += gridDim.x, ++it) {
+    const int par = mixing ? 0 : (it & 1);
+    float* const red = redbase + par * epb * NY * CP;
+    int* const cent = centbase + par * epb;
+    const int64_t e0 = grp * epb - sh, e = e0 + el;
+    // valid rows of the group: lo .. hi - 1 (lo > 0 only in the first group)
+    const int lo = e0 < 0 ? (int)-e0 : 0, hi = (int)(ne - e0 < epb ? ne - e0 : epb);
+    const bool valid = el >= lo && el < hi;
     if (!LAST && !a.last) {
       // The previous group's reads of gTl finished before this barrier pair
       // lets the mixing overwrite it.
@@ -923,16 +961,28 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     // guards the stores. The 32-channel plan keeps the branch: running the
     // extra rows there costs more registers (spills) than the exact wait
     // counts save.
-    const int64_t e0 = grp * epb;
-    const int nval = (int)(ne - e0 < epb ? ne - e0 : epb);
     if (CC == 0 || valid)
-      tp_bwd_edge<LMAX, CC>(a, e0, nval, el, c, gTl + el * NT * CP, CP, in);
+      tp_bwd_edge<LMAX, CC>(a, e0, lo, hi, el, c, gTl + el * NT * CP, CP, in, red + el * rstride);
+    if (c == 0) cent[el] = cur;
+    tp_lds_barrier();
+    if (valid && (el == lo || cent[el] != cent[el - 1])) {
+      float sum[NY];
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) sum[lm] = red[el * rstride + lm * CP + c];
+      for (int e2 = el + 1; e2 < hi && cent[e2] == cur; ++e2)
+#pragma unroll
+        for (int lm = 0; lm < NY; ++lm) sum[lm] += red[e2 * rstride + lm * CP + c];
+      float* ggr = a.ggc + e * (NY * C) + c;
+#pragma unroll
+      for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = sum[lm];
+    }
     // The next group's loads go into the same registers once this group's
     // adjoint is done: their latency then overlaps the next group's staging
     // and mixing (or, for the last layer, other wavefronts' work), and only
     // one set of inputs is live at a time (issuing them before the adjoint
     // kept two sets live and spilled the mixing weights).
     issue(clampg(grp + gridDim.x), ctr, gv, in);
+    cur = ctr;
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
   }
 }
@@ -962,7 +1012,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 
 // Adjoint of the environment sum Gamma_i = nu^-1/2 sum_k e_k (x) Y_k for one
 // centre per wavefront (lanes: channel c, group g of G = 64 / C):
-//   dGamma_i[lm][c] = nu^-1/2 sum_k ggc[k][lm][c]      (groups split the edges)
+//   dGamma_i[lm][c] = nu^-1/2 sum_k ggc[k][lm][c]      (groups split the rows)
+// where the tensor-product adjoint left ggc rows only at the centre's first
+// edge and at every multiple of `run` after it, each holding the sum of the
+// contributions up to the next such row;
 //   de_k[l][c]      = sum_m dGamma_i[lm][c] Y_k[lm]     -> gew[:, gcol + l*C + c]
 //   dY_k[lm]        = sum_c e_k[l][c] dGamma_i[lm][c]   (channel sums spread over lanes)
 // dGamma_i stays in registers between the two passes over the centre's edges.
@@ -971,7 +1024,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(3))) void k
 // next edge's inputs before working on the current one.
 template <int NY, int C>
 __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __restrict__ nedge_p,
-                                                     const int* __restrict__ eoff, const float* __restrict__ ggc,
+                                                     const int* __restrict__ eoff, const int* __restrict__ e0p,
+                                                     int run, const float* __restrict__ ggc,
                                                      const float* __restrict__ esrc, int lde,
                                                      const float* __restrict__ geo, float scale,
                                                      float* __restrict__ gew, int ldgew, int gcol,
@@ -986,19 +1040,15 @@ __global__ __launch_bounds__(256) void k_env_adjoint(int64_t n, const int* __res
   float dg[NY];
 #pragma unroll
   for (int lm = 0; lm < NY; ++lm) dg[lm] = 0.f;
-  int k = b + g;
-  for (; k + 3 * G < e1; k += 4 * G) {  // four edges per group in flight
-    float v[4][NY];
+  // rows: b, then m0, m0 + run, ... below e1 (m0: the first edge after b
+  // whose global index e0 + k is a multiple of run); row q of the centre is
+  // b for q = 0, m0 + (q - 1) run after
+  const int m0 = b + run - (*e0p + b) % run;
+  const int nrow = b < e1 ? 1 + (e1 > m0 ? (e1 - m0 + run - 1) / run : 0) : 0;
+  for (int q = g; q < nrow; q += G) {
+    const int64_t k = q == 0 ? b : m0 + (int64_t)(q - 1) * run;
 #pragma unroll
-    for (int u = 0; u < 4; ++u)
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) v[u][lm] = ggc[((int64_t)(k + u * G) * NY + lm) * C + c];
-#pragma unroll
-    for (int lm = 0; lm < NY; ++lm) dg[lm] += (v[0][lm] + v[1][lm]) + (v[2][lm] + v[3][lm]);
-  }
-  for (; k < e1; k += G) {
-#pragma unroll
-    for (int lm = 0; lm < NY; ++lm) dg[lm] += ggc[((int64_t)k * NY + lm) * C + c];
+    for (int lm = 0; lm < NY; ++lm) dg[lm] += ggc[(k * NY + lm) * C + c];
   }
 #pragma unroll
   for (int o = C; o < 64; o <<= 1)
@@ -1405,16 +1455,18 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
   const Dims& d = m->dims;
   Workspace& ws = ctx->ws;
   const bool last = t == d.T;
-  const TpBwdArgs a{ws.v_nedge, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
+  const TpBwdArgs a{ws.v_nedge, ws.v_e0, ws.v_ei, ws.geo, d.C, t == 1, last, ws.we1, 2 * d.NW, ws.V[t - 1], ws.gam[t],
                     ws.gs, d.nscal * d.C, last ? nullptr : gvin, layer_mix(m, t), ws.ggc, gvout, ws.gew,
                     2 * d.NW, ws.gY, 16 * (d.T + 1)};
-  const size_t lds = tp_lds_bytes(d.C, d.L, true);
+  const size_t lds = tp_lds_bytes(d.C, d.L, true), llds = tp_last_lds_bytes(d.C, d.L);
   // bytes per edge: dE/dV_t, V_{t-1} (w0 and Y for t = 1), the centre index,
   // dE/ds, the dE/dGamma contributions, and dE/dV_{t-1} (t > 1) or dE/dw0
   // plus the w0 part of dE/dY (t = 1); per atom: Gamma read once
   const double vin = t == 1 ? 4.0 * (d.NW + d.NY) : 4.0 * d.NY * d.C;
   const double vout = t == 1 ? 4.0 * d.NW + 4.0 * d.NY : 4.0 * d.NY * d.C;
-  const double bpe = (last ? 0.0 : 4.0 * d.NY * d.C) + vin + 4.0 + 4.0 * d.nscal * d.C + 4.0 * d.NY * d.C + vout;
+  // (the dE/dGamma rows: one run sum per group of 256 / C edges)
+  const double bpe =
+      (last ? 0.0 : 4.0 * d.NY * d.C) + vin + 4.0 + 4.0 * d.nscal * d.C + 4.0 * d.NY * d.C * d.C / 256.0 + vout;
   const int sp = span_begin(ctx, "tp_bwd" + std::to_string(t), m->tp_flop_bwd[t - 1], bpe, 0,
                             4.0 * d.NY * d.C, m->tp_flop_mix[t - 1]);
   // the last layer has no mixing: a lighter kernel keeps more waves
@@ -1422,8 +1474,8 @@ void launch_tp_bwd(nq_ctx* ctx, const nq_model* m, int t, const float* gvin, flo
 #define NQ_TPB(K, LM)                                                                             \
   if (LM == 2 && c32)                                                                             \
     k_tp_bwd<K, 2, true><<<tp_grid(ctx, k_tp_bwd<K, 2, true>, lds, d.C), 256, lds, ctx->stream>>>(a); \
-  else if (LM == 2 && l32) /* no mixing: no LDS */                                                \
-    k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, 0, d.C), 256, 0, ctx->stream>>>(a);     \
+  else if (LM == 2 && l32) /* no mixing: LDS for the run sums only */                             \
+    k_tp_bwd_last32<K><<<tp_grid(ctx, k_tp_bwd_last32<K>, llds, d.C), 256, llds, ctx->stream>>>(a); \
   else                                                                                            \
     k_tp_bwd<K, LM, false><<<tp_grid(ctx, k_tp_bwd<K, LM, false>, lds, d.C), 256, lds, ctx->stream>>>(a)
   switch (site_precision(m, "tp_bwd" + std::to_string(t)) * 2 + (d.L == 2)) {
@@ -1446,11 +1498,12 @@ void launch_env_bwd(nq_ctx* ctx, const nq_model* m, int t) {
   const float* esrc = t == 1 ? ws.we1 + d.NW : ws.e[t];
   const int lde = t == 1 ? 2 * d.NW : d.NW;
   const float scale = (float)d.inv_sqrt_nu;
-  // per edge: the dE/dGamma contributions, e, Y, dE/de and dE/dY written
+  // per edge: the dE/dGamma run sums (one per group of 256 / C edges), e, Y,
+  // dE/de and dE/dY written
   const int sp = span_begin(ctx, "env_bwd" + std::to_string(t), 0,
-                            4.0 * d.NY * d.C + 8.0 * d.NW + 4.0 * d.NY + 4.0 * d.NY, 0, 4.0);
+                            4.0 * d.NY * d.C * d.C / 256.0 + 8.0 * d.NW + 4.0 * d.NY + 4.0 * d.NY, 0, 4.0);
 #define NQ_ENVB(NYV, CV)                                                                                   \
-  k_env_adjoint<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.ggc, esrc, lde, \
+  k_env_adjoint<NYV, CV><<<grid_for(n, 4), 256, 0, ctx->stream>>>(n, ws.v_nedge, ws.v_eoff, ws.v_e0, 256 / d.C, ws.ggc, esrc, lde, \
                                                                   ws.geo, scale, ws.gew, 2 * d.NW, d.NW,       \
                                                                   ws.gY + 16 * t, 16 * (d.T + 1))
   NQ_DISPATCH_NY_C(d.NY, d.C, NQ_ENVB);
