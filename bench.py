@@ -714,7 +714,7 @@ def main():
         [{"name": k["name"], "ms_per_step": k["ms_total"] / args.breakdown_steps,
           "launches_per_step": k["count"] / args.breakdown_steps,
           "method_tflops": k.get("mfma_flop_per_launch", 0.0) / (k["ms_total"] / k["count"] * 1e-3) / 1e12}
-         for k in rep["kernels"]], key=lambda k: -k["ms_per_step"])[:12]
+         for k in rep["kernels"]], key=lambda k: -k["ms_per_step"])
     line["breakdown_ms_per_step"] = sum(k["ms_total"] for k in rep["kernels"]) / args.breakdown_steps
     print(json.dumps(line), flush=True)
 

@@ -969,9 +969,17 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
       float sum[NY];
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) sum[lm] = red[el * rstride + lm * CP + c];
-      for (int e2 = el + 1; e2 < hi && cent[e2] == cur; ++e2)
+      // next row's centre and values read together (one LDS round trip per
+      // row); centres are sorted, so the first row of another centre ends the run
+      for (int e2 = el + 1; e2 < hi; ++e2) {
+        const int ce = cent[e2];
+        float v[NY];
 #pragma unroll
-        for (int lm = 0; lm < NY; ++lm) sum[lm] += red[e2 * rstride + lm * CP + c];
+        for (int lm = 0; lm < NY; ++lm) v[lm] = red[e2 * rstride + lm * CP + c];
+        if (ce != cur) break;
+#pragma unroll
+        for (int lm = 0; lm < NY; ++lm) sum[lm] += v[lm];
+      }
       float* ggr = a.ggc + e * (NY * C) + c;
 #pragma unroll
       for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = sum[lm];
