@@ -588,11 +588,16 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     else if ((t = layer("s")) >= 1 && t <= d.T) { src = ws.s[t]; w = d.nscal * d.C; }
     else if ((t = layer("V")) >= 1 && t < d.T) { src = ws.V[t]; w = d.NY * d.C; }
     else if ((t = layer("x")) >= 0 && t <= d.T) { src = ws.x[t]; w = d.D; }
-    NQ_REQUIRE(src, NQ_ERR_ARG, "unknown buffer name " + s);
+    const bool x0 = s == "x0";  // formed from the two-body pre-activation, not stored
+    NQ_REQUIRE(src || x0, NQ_ERR_ARG, "unknown buffer name " + s);
+    if (x0) w = d.D;
     *rows = r;
     *width = w;
     NQ_REQUIRE(r * w <= cap, NQ_ERR_CAPACITY, "output too small");
-    NQ_HIP(hipMemcpyAsync(out, src, (size_t)r * w * 4, hipMemcpyDeviceToDevice, ctx->stream));
+    if (x0)
+      debug_x0_async(ctx, model, out);
+    else
+      NQ_HIP(hipMemcpyAsync(out, src, (size_t)r * w * 4, hipMemcpyDeviceToDevice, ctx->stream));
     NQ_HIP(hipStreamSynchronize(ctx->stream));
   });
 }

@@ -49,7 +49,9 @@ __device__ inline float residual_adjoint(float g, float y) { return __builtin_fm
 
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
-enum ALoadMode { A_PLAIN = 0, A_SILU = 1, A_CAT = 2, A_GRADSILU = 3 };
+// A_SILU_U: u SiLU(a) with u the row scale, i.e. the two-body output x0
+// formed at use from its stored pre-activation; A_CAT_SILU_U: [u SiLU(a) | s].
+enum ALoadMode { A_PLAIN = 0, A_SILU = 1, A_CAT = 2, A_GRADSILU = 3, A_SILU_U = 4, A_CAT_SILU_U = 5 };
 
 // Raw loads of four consecutive A values of one row, kept in registers until
 // the tile is written to LDS (a K step later), so the loads stay in flight
@@ -72,17 +74,20 @@ struct ALoad {
   // reads column 0 and is zeroed by finish(). Only uniform branches, so the
   // loads of several K steps can be in flight together.
   __device__ inline void fetch(int64_t r, int k, ARaw& o) const {
-    if (mode == A_CAT) {
+    if (mode == A_CAT || mode == A_CAT_SILU_U) {
       const bool second = k >= K0;
       const int k1 = k - K0 < K1 ? k - K0 : 0;
       const float* p = second ? p1 + r * ld1 + k1 : p0 + r * ld0 + k;
       o.v = *reinterpret_cast<const float4*>(p);
+      if (mode == A_CAT_SILU_U) o.f = rs[r * rs_ld];
     } else {
       const int kk = k < K0 ? k : 0;
       o.v = *reinterpret_cast<const float4*>(p0 + r * ld0 + kk);
       if (mode == A_GRADSILU) {
         o.a = *reinterpret_cast<const float4*>(p1 + r * ld1 + kk);
         o.f = rs ? rs[r * rs_ld] : 1.f;
+      } else if (mode == A_SILU_U) {
+        o.f = rs[r * rs_ld];
       }
     }
   }
@@ -91,13 +96,18 @@ struct ALoad {
   // With gu set, rd accumulates this chunk's share of sum_k g SiLU(a), the
   // derivative with respect to the row scale, from the same loaded values.
   __device__ inline float4 finish(const ARaw& o, bool row_ok, int k, float& rd) const {
-    const bool ok = row_ok && k < (mode == A_CAT ? K0 + K1 : K0);
+    const bool ok = row_ok && k < ((mode == A_CAT || mode == A_CAT_SILU_U) ? K0 + K1 : K0);
     float4 v = o.v;
     if (mode == A_SILU) {
       v.x = siluf(v.x);
       v.y = siluf(v.y);
       v.z = siluf(v.z);
       v.w = siluf(v.w);
+    } else if (mode == A_SILU_U || (mode == A_CAT_SILU_U && k < K0)) {
+      v.x = o.f * siluf(v.x);
+      v.y = o.f * siluf(v.y);
+      v.z = o.f * siluf(v.z);
+      v.w = o.f * siluf(v.w);
     } else if (mode == A_GRADSILU) {
       const float f = c * o.f;
       const float sx = sigmoidf_(o.a.x), sy = sigmoidf_(o.a.y), sz = sigmoidf_(o.a.z), sw = sigmoidf_(o.a.w);
@@ -123,6 +133,7 @@ struct Epi {
   const float* x; int ldx;
   const float* rs; int rs_ld;
   int D;
+  int xsilu;  // E_RESIDUAL: x holds a pre-activation; the residual input is u SiLU(x)
 };
 
 // Writes the accumulator tiles of one wavefront through epilogue mode MODE.
@@ -163,6 +174,7 @@ __device__ inline void store_tiles(const Epi& ep, const floatx4 (&acc)[MI][NI], 
             int cc = c < ep.N0 ? c : 0;
             if constexpr (MODE == E_LATENT_BWD) cc = cc < ep.D ? cc : 0;
             in[jj][q] = src[cc];
+            if (MODE == E_RESIDUAL && ep.xsilu) in[jj][q] = rsv[q] * siluf(in[jj][q]);
           }
         }
       }
@@ -478,6 +490,8 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   constexpr int A4 = RT * CPR;                 // ... per tile
   constexpr int NA = (A4 + 511) / 512;
   constexpr bool GR = AMODE == A_GRADSILU;
+  constexpr bool CAT = AMODE == A_CAT || AMODE == A_CAT_SILU_U;
+  constexpr bool SU = AMODE == A_SILU_U || AMODE == A_CAT_SILU_U;  // u SiLU(a) of the (first) source
   constexpr bool XIN = EMODE == E_RESIDUAL || EMODE == E_LATENT_BWD;  // FP32 copy of the primary source
   __shared__ __attribute__((aligned(16))) bf16 As[2][H * RT * LDH];
   __shared__ __attribute__((aligned(16))) float Xs[XIN ? 2 : 1][XIN ? RT * LDW : 4];
@@ -517,7 +531,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   // 4 (idx % CPR) .. +3 with idx = tid + 512 q)
   struct Stage {
     float4 rv[NA], rg[GR ? NA : 1], in[ADD ? NE : 1];
-    float rf[GR ? NA : 1], ru;  // ru: the epilogue row scale, or dE/du of rows (wave + 8 lane) (GR)
+    float rf[GR || SU ? NA : 1], ru;  // ru: the epilogue row scale, or dE/du of rows (wave + 8 lane) (GR)
   };
   Stage s0, s1;  // s1 is used only with two tiles in flight (PF = 2)
   // dE/du of the rows of a tile (empty without gu)
@@ -549,10 +563,11 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       const int idx = (t + 512 * q) % A4;
       const int r = idx / CPR < lim ? idx / CPR : lim;
       const int k = (idx % CPR) * 4;
-      if constexpr (AMODE == A_CAT) {
+      if constexpr (CAT) {
         const float* p = k >= ld.K0 ? b1 + (unsigned)(r * ld.ld1 + (k - ld.K0 < ld.K1 ? k - ld.K0 : 0))
                                     : b0 + (unsigned)(r * ld.ld0 + k);
         S.rv[q] = *reinterpret_cast<const float4*>(p);
+        if constexpr (SU) S.rf[q] = brs[(unsigned)(r * rsl)];
       } else {
         const int kk = k < ld.K0 ? k : 0;
         S.rv[q] = *reinterpret_cast<const float4*>(b0 + (unsigned)(r * ld.ld0 + kk));
@@ -560,6 +575,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
           S.rg[q] = *reinterpret_cast<const float4*>(b1 + (unsigned)(r * ld.ld1 + kk));
           S.rf[q] = brs[(unsigned)(r * rsl)];
         }
+        if constexpr (SU) S.rf[q] = brs[(unsigned)(r * rsl)];
       }
     }
   };
@@ -581,8 +597,17 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     for (int q = 0; q < NA; ++q) {
       const int idx = t + 512 * q;
       const int i2 = idx % A4, rr = i2 / CPR, k = (i2 % CPR) * 4;
-      const bool ok = row0 + rr < nrows && k < (AMODE == A_CAT ? ld.K0 + ld.K1 : ld.K0);
+      const bool ok = row0 + rr < nrows && k < (CAT ? ld.K0 + ld.K1 : ld.K0);
       float4 v = S.rv[q];
+      // x0 = u SiLU(a) is formed before the FP32 copy (the residual's input)
+      if constexpr (SU) {
+        if (AMODE == A_SILU_U || k < ld.K0) {
+          v.x = S.rf[q] * siluf(v.x);
+          v.y = S.rf[q] * siluf(v.y);
+          v.z = S.rf[q] * siluf(v.z);
+          v.w = S.rf[q] * siluf(v.w);
+        }
+      }
       if constexpr (XIN)
         if (idx < A4 && k < ld.K0)
           *reinterpret_cast<float4*>(&xdst[rr * LDW + k]) = ok ? v : make_float4(0.f, 0.f, 0.f, 0.f);

@@ -17,8 +17,10 @@ namespace {
 // through LDS); the autotuner picks one per product.
 #define NQ_WS_LIST(X)                     \
   X(11, 2, A_CAT, E_RESIDUAL, 2)          \
+  X(11, 2, A_CAT_SILU_U, E_RESIDUAL, 2)   \
   X(8, 3, A_GRADSILU, E_LATENT_BWD, 1)    \
-  X(4, 2, A_SILU, E_STORE_X0, 2)          \
+  X(4, 2, A_SILU, E_STORE, 2)             \
+  X(8, 2, A_SILU_U, E_STORE, 2)           \
   X(6, 2, A_PLAIN, E_ADD, 2)              \
   X(3, 2, A_PLAIN, E_ADD, 2)              \
   X(8, 1, A_GRADSILU, E_STORE, 2)         \

@@ -271,6 +271,9 @@ void ring_polymer_async(hipStream_t s, const double* pos, const double* inv_mass
                         double omega_p, const double box[3], double* forces, double* e_bond, double* energy);
 void md_ekin_async(hipStream_t s, const double* vel, const double* inv_mass, int64_t n,
                    double* out);
+// out[e][c] = u_e SiLU(a[e][c]) over the last evaluation's edges: the two-body
+// output x0, which the pipeline forms at use instead of storing (stage export).
+void debug_x0_async(nq_ctx* ctx, const nq_model* m, float* out);
 // Device address of the fixed ring-polymer bond-energy array on `device`
 // (NQ_RING_POLYMER_NOALLOC_MAX doubles), looked up once per device; the
 // device must be current.

@@ -1299,6 +1299,8 @@ double gemm_bytes_per_row(const ALoad& ld, const Epi& ep) {
   double a = 0;
   switch (ld.mode) {
     case A_CAT: a = ld.K0 + ld.K1; break;
+    case A_CAT_SILU_U: a = ld.K0 + ld.K1 + 1; break;
+    case A_SILU_U: a = ld.K0 + 1; break;
     case A_GRADSILU: a = (ld.ld0 ? ld.K0 : 0) + ld.K0 + (ld.rs ? 1 : 0) + (ld.gu ? 2 : 0); break;
     default: a = ld.K0;
   }
@@ -1368,8 +1370,16 @@ void gemm(nq_ctx* ctx, const nq_model* m, const Lin& L, bool bwd, const ALoad& l
 
 ALoad a_plain(const float* p, int ld, int K) { return ALoad{A_PLAIN, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }
 ALoad a_silu(const float* p, int ld, int K) { return ALoad{A_SILU, p, ld, K, nullptr, 0, 0, nullptr, 0, 1.f, nullptr}; }
+// u SiLU(a) of pre-activations a with the row scale u (x0 formed at use)
+ALoad a_silu_u(const float* p, int ld, int K, const float* u) {
+  return ALoad{A_SILU_U, p, ld, K, nullptr, 0, 0, u, kGeo, 1.f, nullptr};
+}
 ALoad a_cat(const float* p, int ld, int K, const float* q, int ldq, int Kq) {
   return ALoad{A_CAT, p, ld, K, q, ldq, Kq, nullptr, 0, 1.f, nullptr};
+}
+// [u SiLU(a) | q]
+ALoad a_cat_silu_u(const float* p, int ld, int K, const float* q, int ldq, int Kq, const float* u) {
+  return ALoad{A_CAT_SILU_U, p, ld, K, q, ldq, Kq, u, kGeo, 1.f, nullptr};
 }
 ALoad a_gradsilu(const float* g, int ldg, int K, const float* a, int lda, const float* rs, float c,
                  float* gu = nullptr) {
@@ -1563,7 +1573,25 @@ __global__ void k_chunk_offsets(const int* __restrict__ eoff, int64_t a0, int64_
   c_eoff[i] = eoff[a0 + i] - eoff[a0];
 }
 
+// x0[e][c] = u_e SiLU(a[e][c]) (the stage export of x0; the pipeline forms it
+// at use)
+__global__ void k_x0(const int* __restrict__ nedge_p, const float* __restrict__ a, int D,
+                     const float* __restrict__ geo, float* __restrict__ out) {
+  const int64_t k = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t e = k / D;
+  if (e >= *nedge_p) return;
+  out[k] = geo[e * kGeo + 1] * siluf(a[k]);
+}
+
 }  // namespace
+
+void debug_x0_async(nq_ctx* ctx, const nq_model* m, float* out) {
+  const Workspace& ws = ctx->ws;
+  const Dims& d = m->dims;
+  k_x0<<<(unsigned)cdiv(ws.cap * d.D, 256), 256, 0, ctx->stream>>>(ws.v_nedge, ws.a_tb[d.n_tb - 1], d.D, ws.geo,
+                                                                   out);
+  NQ_HIP(hipGetLastError());
+}
 
 void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms, bool activations) {
   Workspace& ws = ctx->ws;
@@ -1654,7 +1682,7 @@ void ws_ensure(nq_ctx* ctx, const nq_model* m, int64_t cap_all, int64_t n_atoms,
   ws.V.assign(d.T + 1, nullptr);
   ws.e.assign(d.T + 1, nullptr);
   ws.a_lat.assign(d.T + 1, {});
-  ws.x[0] = fbuf(cap, d.D);
+  // x[0] stays null: x0 = u SiLU(a) is formed from the two-body pre-activation
   for (int t = 1; t <= d.T; ++t) {
     if (t > 1) ws.e[t] = fbuf(cap, d.NW);
     ws.gam[t] = fbuf(n_atoms, d.NY * d.C);
@@ -1733,21 +1761,16 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
                                                    ctx->nl.flags.as<int>());
     span_end(ctx, sp_);
   }
-  // two-body MLP; the last layer stores x0 = u * SiLU(a)
+  // two-body MLP; x0 = u * SiLU(a) of the last layer is not stored: its two
+  // readers (the [w0 | e1] product and the first latent layer, operand and
+  // residual) form it from the stored pre-activation a
   for (int k = 0; k < d.n_tb; ++k) {
     const Lin& L = *m->tb[k];
     ALoad ld = k == 0 ? a_plain(ws.h0, ws.K0p, ws.K0p) : a_silu(ws.a_tb[k - 1], d.tb[k - 1], d.tb[k - 1]);
-    Epi ep = e_store(ws.a_tb[k], d.tb[k], d.tb[k]);
-    if (k == d.n_tb - 1) {
-      ep.mode = E_STORE_X0;
-      ep.o1 = ws.x[0];
-      ep.ld1 = d.D;
-      ep.rs = u;
-      ep.rs_ld = kGeo;
-    }
-    gemm(ctx, m, L, false, ld, ep, "fwd.twobody." + std::to_string(k));
+    gemm(ctx, m, L, false, ld, e_store(ws.a_tb[k], d.tb[k], d.tb[k]), "fwd.twobody." + std::to_string(k));
   }
-  gemm(ctx, m, m->v0e1, false, a_plain(ws.x[0], d.D, d.D), e_store(ws.we1, 2 * d.NW, 2 * d.NW), "fwd.v0env1");
+  const float* a_x0 = ws.a_tb[d.n_tb - 1];
+  gemm(ctx, m, m->v0e1, false, a_silu_u(a_x0, d.D, d.D, u), e_store(ws.we1, 2 * d.NW, 2 * d.NW), "fwd.v0env1");
   const float inv_sqrt_nu = (float)d.inv_sqrt_nu;
   for (int t = 1; t <= d.T; ++t) {
     if (t > 1)
@@ -1769,17 +1792,19 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
     // latent MLP on [x | s]; the last layer applies the residual update
     for (int k = 0; k < d.n_lat; ++k) {
       const Lin& L = *m->lat[t - 1][k];
-      ALoad ld = k == 0 ? a_cat(ws.x[t - 1], d.D, d.D, ws.s[t], d.nscal * d.C, d.nscal * d.C)
-                        : a_silu(ws.a_lat[t][k - 1], d.lat[k - 1], d.lat[k - 1]);
+      ALoad ld = k > 0    ? a_silu(ws.a_lat[t][k - 1], d.lat[k - 1], d.lat[k - 1])
+                 : t == 1 ? a_cat_silu_u(a_x0, d.D, d.D, ws.s[t], d.nscal * d.C, d.nscal * d.C, u)
+                          : a_cat(ws.x[t - 1], d.D, d.D, ws.s[t], d.nscal * d.C, d.nscal * d.C);
       Epi ep = e_store(ws.a_lat[t][k], d.lat[k], d.lat[k]);
       if (k == d.n_lat - 1) {
         ep.mode = E_RESIDUAL;
         ep.o1 = ws.x[t];
         ep.ld1 = d.D;
-        ep.x = ws.x[t - 1];
+        ep.x = t == 1 ? a_x0 : ws.x[t - 1];
         ep.ldx = d.D;
         ep.rs = u;
         ep.rs_ld = kGeo;
+        ep.xsilu = t == 1;
       }
       gemm(ctx, m, L, false, ld, ep, "fwd.latent" + std::to_string(t) + "." + std::to_string(k));
     }
