@@ -179,3 +179,45 @@ def test_graph_recaptured_after_list_change():
     assert pot.graph_captures() == 2
     pot.close()
     fresh.close()
+
+
+@pytest.mark.parametrize("prec", ["fp32", "bf16x3"])
+def test_300K_run_collapses_like_the_oracle(prec):
+    """NVE at 300 K on the 1,024-atom system, one step per call, against the
+    FP64 oracle's own trajectory (tests/golden/c3_oracle_nve.json, written by
+    c3_oracle_nve.py): with random weights the surface has no repulsive core,
+    so both trajectories heat up as atoms fall together until a pair is closer
+    than 0.1 A, where the library stops with NQ_ERR_NUMERIC. The kinetic
+    energies agree step by step while the trajectories are close, and the
+    library stops within a few steps of the oracle's collapse."""
+    import json
+    import os
+
+    from paper_2303_08169_amd.binding import NQError
+    from paper_2303_08169_amd.potential import Potential
+    with open(os.path.join(os.path.dirname(__file__), "golden", "c3_oracle_nve.json")) as f:
+        g = json.load(f)
+    cf, pos, z, L, w = system("nh3_1024_l2")
+    assert g["workload"] == "nh3_1024_l2" and g["velocity_seed"] == 200 and g["dt_fs"] == 0.5
+    pot = Potential(cf.model, w, prec)
+    P, V, IM, Z, m, v0 = _state(pos, z, g["temperature_K"], g["velocity_seed"])
+    E, F = pot.energy_forces(P, Z, L)
+    assert abs(E.item() - g["epot0"]) <= 1e-5 * abs(g["epot0"])
+    ep = torch.zeros(1, dtype=torch.float64, device="cuda")
+    ek = torch.zeros(1, dtype=torch.float64, device="cuda")
+    stop, ekin = None, []
+    for s in range(1, g["collapsed_at_step"] + 20):
+        try:
+            pot.step(P, V, IM, Z, L, g["dt_fs"], 1, F, ep, ek)
+            torch.cuda.synchronize()
+        except NQError as e:
+            assert e.status == -4, str(e)  # NQ_ERR_NUMERIC: two atoms closer than 0.1 A
+            stop = s
+            break
+        ekin.append(ek.item())
+    pot.close()
+    print(f"{prec}: stopped at step {stop}, oracle at {g['collapsed_at_step']}", flush=True)
+    ref = np.array([st["ekin"] for st in g["steps"]])
+    # the first 50 steps (25 fs): the trajectories have not separated yet
+    np.testing.assert_allclose(ekin[:50], ref[:50], rtol=1e-3)
+    assert stop is not None and abs(stop - g["collapsed_at_step"]) <= 5
