@@ -69,48 +69,73 @@ __device__ inline void envelope(float x, int p, float& u, float& du) {
 }
 
 // ------------------------------------------------------------------ geometry
-__global__ void k_geometry(const int* __restrict__ nedge_p, const float4* __restrict__ rij,
-                           const int* __restrict__ ei, const int* __restrict__ ej, int64_t a0,
-                           const int32_t* __restrict__ species, int S, int nb, int p, float rc,
-                           int K0p, float* __restrict__ geo, float* __restrict__ h0, int* __restrict__ flags) {
-  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (e >= *nedge_p) return;
-  const float4 r = rij[e];
-  const float d = r.w, inv = 1.f / d;
-  const float x = r.x * inv, y = r.y * inv, z = r.z * inv;
-  float u, du;
-  envelope(d / rc, p, u, du);
-  float Y[9];
-  sph(x, y, z, Y);
-  float* g = geo + e * kGeo;
-  g[0] = d;
-  g[1] = u;
-  g[2] = x;
-  g[3] = y;
-  g[4] = z;
+// One thread per edge computes the edge's geometry row and two-body input
+// row into LDS (rows padded by one word: no bank conflicts); the block then
+// writes its rows as contiguous 16-byte chunks (stored directly, a thread's
+// rows are 64 and 128 bytes apart: one 4-byte store per value, the lanes
+// of a store 64 or 128 bytes apart).
+__global__ __launch_bounds__(256) void k_geometry(const int* __restrict__ nedge_p, const float4* __restrict__ rij,
+                                                  const int* __restrict__ ei, const int* __restrict__ ej, int64_t a0,
+                                                  const int32_t* __restrict__ species, int S, int nb, int p, float rc,
+                                                  int K0p, float* __restrict__ geo, float* __restrict__ h0,
+                                                  int* __restrict__ flags) {
+  extern __shared__ float gl_lds[];  // [256][kGeo + 1], then [256][K0p + 1]
+  const int t = threadIdx.x;
+  const int64_t e0 = (int64_t)blockIdx.x * 256, ne = *nedge_p;
+  if (e0 >= ne) return;  // the whole block
+  const int nrow = (int)(ne - e0 < 256 ? ne - e0 : 256);
+  float* g = gl_lds + t * (kGeo + 1);
+  float* h = gl_lds + 256 * (kGeo + 1) + t * (K0p + 1);
+  if (t < nrow) {
+    const int64_t e = e0 + t;
+    const float4 r = rij[e];
+    const float d = r.w, inv = 1.f / d;
+    const float x = r.x * inv, y = r.y * inv, z = r.z * inv;
+    float u, du;
+    envelope(d / rc, p, u, du);
+    float Y[9];
+    sph(x, y, z, Y);
+    g[0] = d;
+    g[1] = u;
+    g[2] = x;
+    g[3] = y;
+    g[4] = z;
 #pragma unroll
-  for (int k = 0; k < 9; ++k) g[kGeoY + k] = Y[k];
-  g[14] = 0.f;
-  g[15] = 0.f;
-  float* h = h0 + e * K0p;
-  const int zi = species[a0 + ei[e]], zj = species[ej[e]];
-  if (zi < 0 || zi >= S || zj < 0 || zj >= S) flags[5] = 1;
-  for (int k = 0; k < S; ++k) {
-    h[k] = (k == zi) ? 1.f : 0.f;
-    h[S + k] = (k == zj) ? 1.f : 0.f;
+    for (int k = 0; k < 9; ++k) g[kGeoY + k] = Y[k];
+    g[14] = 0.f;
+    g[15] = 0.f;
+    const int zi = species[a0 + ei[e]], zj = species[ej[e]];
+    if (zi < 0 || zi >= S || zj < 0 || zj >= S) flags[5] = 1;
+    for (int k = 0; k < S; ++k) {
+      h[k] = (k == zi) ? 1.f : 0.f;
+      h[S + k] = (k == zj) ? 1.f : 0.f;
+    }
+    const float pref = 2.f / rc, w = 3.14159265358979323846f / rc;
+    // sin(n w d) for n = 1..nb by the angle-addition recurrence from one sincos
+    float s1, c1;
+    sincosf(w * d, &s1, &c1);
+    float sn = s1, cn = c1;
+    for (int n = 1; n <= nb; ++n) {
+      h[2 * S + n - 1] = pref * sn * inv * u;
+      const float tt = sn * c1 + cn * s1;
+      cn = cn * c1 - sn * s1;
+      sn = tt;
+    }
+    for (int k = 2 * S + nb; k < K0p; ++k) h[k] = 0.f;
   }
-  const float pref = 2.f / rc, w = 3.14159265358979323846f / rc;
-  // sin(n w d) for n = 1..nb by the angle-addition recurrence from one sincos
-  float s1, c1;
-  sincosf(w * d, &s1, &c1);
-  float sn = s1, cn = c1;
-  for (int n = 1; n <= nb; ++n) {
-    h[2 * S + n - 1] = pref * sn * inv * u;
-    const float t = sn * c1 + cn * s1;
-    cn = cn * c1 - sn * s1;
-    sn = t;
+  __syncthreads();
+  constexpr int GC = kGeo / 4;
+  for (int i = t; i < nrow * GC; i += 256) {
+    const int rr = i / GC, c = (i % GC) * 4;
+    const float* src = gl_lds + rr * (kGeo + 1) + c;
+    *reinterpret_cast<float4*>(geo + (e0 + rr) * kGeo + c) = make_float4(src[0], src[1], src[2], src[3]);
   }
-  for (int k = 2 * S + nb; k < K0p; ++k) h[k] = 0.f;
+  const int HC = K0p / 4;
+  for (int i = t; i < nrow * HC; i += 256) {
+    const int rr = i / HC, c = (i % HC) * 4;
+    const float* src = gl_lds + 256 * (kGeo + 1) + rr * (K0p + 1) + c;
+    *reinterpret_cast<float4*>(h0 + (e0 + rr) * K0p + c) = make_float4(src[0], src[1], src[2], src[3]);
+  }
 }
 
 // ------------------------------------------------------------------ environment sums
@@ -1756,7 +1781,8 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
   {
     // per edge: r_ij and d, indices, species, geo row and two-body input row written
     const int sp_ = span_begin(ctx, "geometry", 0, 16.0 + 8.0 + 8.0 + 4.0 * kGeo + 4.0 * ws.K0p);
-    k_geometry<<<grid_for(cap, 256), 256, 0, s>>>(ne, ws.v_rij, ws.v_ei, ws.v_ej, ws.v_a0,
+    k_geometry<<<grid_for(cap, 256), 256, 256 * (kGeo + 1 + ws.K0p + 1) * sizeof(float), s>>>(
+        ne, ws.v_rij, ws.v_ei, ws.v_ej, ws.v_a0,
                                                         species, d.S, d.nb, d.p, (float)d.rc, ws.K0p, ws.geo, ws.h0,
                                                    ctx->nl.flags.as<int>());
     span_end(ctx, sp_);
