@@ -187,6 +187,47 @@ __device__ inline void mix_fwd(const FwdB<KIND, W>& B, const float* Tl, int64_t 
   }
 }
 
+// mix_fwd from T already split into BF16 in LDS: hi rows [edge][NT][CPH]
+// (CPH = C + 8 values) and, for BF16X3, lo rows tlo values further. The
+// fragments are the same values load_a would split, so the products are too.
+template <int KIND, int W>
+__device__ inline void mix_fwd_split(const FwdB<KIND, W>& B, const bf16* Th, int tlo, int64_t e0, int64_t ne,
+                                     float* __restrict__ vout, int lane) {
+  static_assert(KIND == G_BF16 || KIND == G_BF16X3, "BF16 kinds only");
+  constexpr int CPH = C + 8;
+  const __amdgpu_buffer_rsrc_t VR = buffer_rsrc(vout + e0 * NY * C, (ne - e0 < EPB ? ne - e0 : EPB) * NY * C * 4);
+#pragma unroll
+  for (int j = 0; j < kFwdN[W]; ++j) {
+    const int l3 = kFwd[W][j].l3, ct = kFwd[W][j].ct, nm = 2 * l3 + 1, R = EPB * nm;
+    const int n = 16 * ct + (lane & 15);
+#pragma unroll
+    for (int rt = 0; rt < RT[l3]; ++rt) {
+      const int r = rt * 16 + (lane & 15);
+      const bool rv = r < R;
+      const int el = rv ? r / nm : 0, m = rv ? r % nm : 0;
+      floatx4 acc = {0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int ks = 0; ks < 4; ++ks) {
+        if (ks >= NP[l3]) continue;  // 32-deep slice ks covers path p = ks
+        const bf16* h = Th + (el * NT + TOFF[l3][ks] + m) * CPH + (lane >> 4) * 8;
+        AFrag<KIND> A;
+        bf16x8 z;
+#pragma unroll
+        for (int k = 0; k < 8; ++k) z[k] = (bf16)0.f;
+        A.h = rv ? *reinterpret_cast<const bf16x8*>(h) : z;
+        if constexpr (KIND == G_BF16X3) A.l = rv ? *reinterpret_cast<const bf16x8*>(h + tlo) : z;
+        acc = mma_frag<KIND>(acc, A, B.f[j * 4 + ks]);
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = rt * 16 + 4 * (lane >> 4) + q;
+        const unsigned off = rr < R ? (unsigned)(((rr / nm) * NY + l3 * l3 + rr % nm) * C + n) * 4 : kOutOfRange;
+        buf_store(acc[q], VR, off);
+      }
+    }
+  }
+}
+
 constexpr bool bwd_has(int W, int l3) {
   for (int j = 0; j < kBwdN[W]; ++j)
     if (kBwd[W][j].l3 == l3) return true;

@@ -515,8 +515,10 @@ static_assert(Paths<2>::pi.toff[0][0] == mix32::TOFF[0][0] && Paths<2>::pi.toff[
 // group's (256 / C) edges x (NT, plus NY for the adjoint) components.
 inline size_t tp_lds_bytes(int C, int L, bool adjoint) {
   const int NT = L == 1 ? 8 : 35, NY = (L + 1) * (L + 1);
-  // the adjoint adds two buffers of the group's edge centres (run sums)
-  return (size_t)(256 / C) * ((C + 4) * (NT + (adjoint ? NY : 0)) + (adjoint ? 2 : 0)) * sizeof(float);
+  // the adjoint adds two buffers of the group's edge centres (run sums); the
+  // forward's T rows are C + 4 floats, or two rows of C + 8 BF16 values
+  if (!adjoint) return (size_t)(256 / C) * NT * (C + 8) * sizeof(float);
+  return (size_t)(256 / C) * ((C + 4) * (NT + NY) + 2) * sizeof(float);
 }
 // Dynamic LDS of the last layer's 32-channel adjoint: two alternating buffers
 // of the group's dE/dGamma contributions and of its edge centres.
@@ -566,9 +568,12 @@ __device__ inline void tp_fwd_load(const TpFwdArgs& a, int64_t e, int ctr, int c
 // edge is row el of the group; stores past them are dropped, so no branch
 // makes the compiler's wait counts for the prefetched loads inexact). CC:
 // channel count if known at compile time, else 0.
-template <int LMAX, int CC>
+// TS: the LDS form of T: 0 FP32 rows (stride CP floats); 1 BF16 rows, 2 BF16
+// hi rows and, tlo elements further, lo rows (stride CP BF16 values), split
+// here once instead of by every wavefront that reads them for the mixing.
+template <int LMAX, int CC, int TS = 0>
 __device__ inline void tp_fwd_edge(const TpFwdArgs& a, __amdgpu_buffer_rsrc_t S, int el, bool valid, int c,
-                                   float* Trow, int CP, const TpFwdIn<LMAX>& in) {
+                                   void* Trow, int CP, const TpFwdIn<LMAX>& in, int tlo = 0) {
   const int C = CC > 0 ? CC : a.C;
   constexpr int NY = TPSize<LMAX>::NY;
   float V[NY];
@@ -586,7 +591,17 @@ __device__ inline void tp_fwd_edge(const TpFwdArgs& a, __amdgpu_buffer_rsrc_t S,
           const float cgv = kCG.v[l1][l2][l3][m1][m2][m3];
           if (cgv != 0.f) acc += cgv * V[l1 * l1 + m1] * in.G[l2 * l2 + m2];
         }
-      if (Trow) Trow[(toff + m3) * CP + c] = valid ? acc : 0.f;  // (null: no mixing follows)
+      if (Trow) {  // (null: no mixing follows)
+        const float v = valid ? acc : 0.f;
+        if constexpr (TS == 0) {
+          static_cast<float*>(Trow)[(toff + m3) * CP + c] = v;
+        } else {
+          bf16* tr = static_cast<bf16*>(Trow) + (toff + m3) * CP + c;
+          const bf16 h = (bf16)v;
+          tr[0] = h;
+          if constexpr (TS == 2) tr[tlo] = (bf16)(v - (float)h);
+        }
+      }
       if (l3 == 0) buf_store(acc, S, srow + (unsigned)(qs * C) * 4);
     }
   });
@@ -604,9 +619,14 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   // MW = -2: the last layer (no mixing) of a 32-channel model
   constexpr int CC = MW >= 0 || MW == -2 ? mix32::C : 0;
   const int C = CC > 0 ? CC : a.C;
-  const int epb = 256 / C, CP = C + 4;
+  // the 32-channel plan keeps T in LDS already split into the BF16 operand(s)
+  // of the mixing (rows of CPH values); otherwise as FP32 rows of CP floats
+  constexpr int TS = MW >= 0 && KIND != G_F32 ? (KIND == G_BF16X3 ? 2 : 1) : 0;
+  const int epb = 256 / C, CP = C + 4, CPH = C + 8;
   const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
   float* Tl = nq_dyn_lds;
+  bf16* Th = reinterpret_cast<bf16*>(nq_dyn_lds);
+  const int tlo = epb * NT * CPH;  // lo rows after the hi rows
   const int64_t ne = *a.nedge_p;
   const int64_t ngroups = (ne + epb - 1) / epb;
   mix32::FwdB<KIND, (MW < 0 ? 0 : MW)> B;
@@ -635,12 +655,17 @@ __device__ inline void tp_fwd_loop(const TpFwdArgs& a) {
   for (; grp < ngroups; grp += gridDim.x) {
     const int64_t e = grp * epb + el, e0 = grp * epb;
     const __amdgpu_buffer_rsrc_t S = buffer_rsrc(a.s + e0 * a.lds, (ne - e0 < epb ? ne - e0 : epb) * a.lds * 4);
-    tp_fwd_edge<LMAX, CC>(a, S, el, e < ne, c, MW == -2 ? nullptr : Tl + el * NT * CP, CP, in);
+    if constexpr (TS == 0)
+      tp_fwd_edge<LMAX, CC, 0>(a, S, el, e < ne, c, MW == -2 ? nullptr : Tl + el * NT * CP, CP, in);
+    else
+      tp_fwd_edge<LMAX, CC, TS>(a, S, el, e < ne, c, Th + el * NT * CPH, CPH, in, tlo);
     issue(clampg(grp + gridDim.x), ctr, in);
     ctr = a.ei[edge_of(clampg(grp + 2 * gridDim.x))];
     if (MW == -2 || a.last) continue;
     __syncthreads();
-    if constexpr (MW >= 0)
+    if constexpr (TS > 0)
+      mix32::mix_fwd_split<KIND, MW>(B, Th, tlo, grp * epb, ne, a.vout, lane);
+    else if constexpr (MW >= 0)
       mix32::mix_fwd<KIND, MW>(B, Tl, grp * epb, ne, a.vout, lane);
     else
       mix_fwd<KIND, LMAX>(Tl, epb, C, grp * epb, ne, a.W, a.vout);
