@@ -707,8 +707,15 @@ __global__ __launch_bounds__(256) void k_edge_energy(const int* __restrict__ ned
   const int l = threadIdx.x % 16;
   float acc = 0.f;
   const bool valid = e < *nedge_p;
-  if (valid)
-    for (int k = l; k < K; k += 16) acc += siluf(a[e * lda + k]) * wout[k];
+  // 16-byte loads (K and lda are multiples of 16), two chunks in flight
+  if (valid) {
+#pragma unroll 2
+    for (int k = 4 * l; k < K; k += 64) {
+      const float4 v = *reinterpret_cast<const float4*>(a + e * lda + k);
+      const float4 w = *reinterpret_cast<const float4*>(wout + k);
+      acc += siluf(v.x) * w.x + siluf(v.y) * w.y + siluf(v.z) * w.z + siluf(v.w) * w.w;
+    }
+  }
 #pragma unroll
   for (int o = 8; o >= 1; o >>= 1) acc += __shfl_xor(acc, o, 16);
   if (valid && l == 0) eij[e] = sigma * acc;
