@@ -40,7 +40,7 @@ extern "C" {
 typedef enum {
   NQ_OK = 0,
   NQ_ERR_ARG = -1,          /* bad pointer, size, species or geometry argument */
-  NQ_ERR_UNSUPPORTED = -2,  /* model shape or option this build does not support */
+  NQ_ERR_UNSUPPORTED = -2,  /* model shape or option the library does not support */
   NQ_ERR_CAPACITY = -3,     /* neighbour-list row or edge capacity exceeded */
   NQ_ERR_NUMERIC = -4,      /* non-finite value or coincident atoms detected */
   NQ_ERR_DEVICE = -5,       /* HIP runtime error */

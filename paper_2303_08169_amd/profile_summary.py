@@ -271,7 +271,7 @@ def main(argv=None):
            "", f"{evals} evaluations of {prof['edges']:,} edges between two marker kernels "
            "(`bench.py --profile-evals`), averaged per evaluation.", ""]
     if cmds:
-        out += ["Commands (repository root R on the GPU box; one counter set per run):", "", "```", cmds, "```", ""]
+        out += ["Commands (R: the repository root on the machine that ran them; one counter set per run):", "", "```", cmds, "```", ""]
     if "fetch_scale" in rec:
         out += [f"HBM bytes = 1024 x (FETCH_SIZE x {rec['fetch_scale']:.4f} + WRITE_SIZE x {rec['write_scale']:.4f}); "
                 f"the factors make a plain device copy of {a.copy_bytes / 2**20:,.0f} MiB read and write exactly that "
