@@ -268,5 +268,47 @@ __device__ inline void mix_bwd(const BwdB<KIND, W>& B, const float* gVl, float* 
   }
 }
 
+// mix_bwd from dE/dV already split into BF16 in LDS: hi rows [edge][NY][CPH]
+// (CPH = C + 8 values) and, for BF16X3, lo rows glo values further. The
+// fragments are the same values load_a would split, so the products are too.
+template <int KIND, int W>
+__device__ inline void mix_bwd_split(const BwdB<KIND, W>& B, const bf16* gVh, int glo, float* gTl, int lane) {
+  static_assert(KIND == G_BF16 || KIND == G_BF16X3, "BF16 kinds only");
+  constexpr int CPH = C + 8;
+#pragma unroll
+  for (int l3 = 2; l3 >= 0; --l3) {
+    if (!bwd_has(W, l3)) continue;
+    const int nm = 2 * l3 + 1, R = EPB * nm;
+#pragma unroll
+    for (int rt = 0; rt < RT[l3]; ++rt) {
+      const int r = rt * 16 + (lane & 15);
+      const bool rv = r < R;
+      const int el = rv ? r / nm : 0, m = rv ? r % nm : 0;
+      const bf16* h = gVh + (el * NY + l3 * l3 + m) * CPH + (lane >> 4) * 8;
+      AFrag<KIND> A;
+      bf16x8 z;
+#pragma unroll
+      for (int k = 0; k < 8; ++k) z[k] = (bf16)0.f;
+      A.h = rv ? *reinterpret_cast<const bf16x8*>(h) : z;
+      if constexpr (KIND == G_BF16X3) A.l = rv ? *reinterpret_cast<const bf16x8*>(h + glo) : z;
+      int dst[4];  // LDS row offsets of this lane's four output rows (-1: past the group)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int rr = rt * 16 + 4 * (lane >> 4) + q;
+        dst[q] = rr < R ? ((rr / nm) * NT + rr % nm) * CP : -1;
+      }
+#pragma unroll
+      for (int j = 0; j < kBwdN[W]; ++j) {
+        if (kBwd[W][j].l3 != l3) continue;
+        const int n = 16 * kBwd[W][j].ct + (lane & 15), p = n / C, c = n % C;
+        const floatx4 acc = mma_frag<KIND>(floatx4{0.f, 0.f, 0.f, 0.f}, A, B.f[j]);
+#pragma unroll
+        for (int q = 0; q < 4; ++q)
+          if (dst[q] >= 0) gTl[dst[q] + TOFF[l3][p] * CP + c] = acc[q];
+      }
+    }
+  }
+}
+
 }  // namespace mix32
 }  // namespace nq

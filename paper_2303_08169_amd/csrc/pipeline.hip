@@ -517,8 +517,9 @@ inline size_t tp_lds_bytes(int C, int L, bool adjoint) {
   const int NT = L == 1 ? 8 : 35, NY = (L + 1) * (L + 1);
   // the adjoint adds two buffers of the group's edge centres (run sums); the
   // forward's T rows are C + 4 floats, or two rows of C + 8 BF16 values
+  // (the adjoint's dE/dV rows likewise: two rows of C + 8 BF16 values)
   if (!adjoint) return (size_t)(256 / C) * NT * (C + 8) * sizeof(float);
-  return (size_t)(256 / C) * ((C + 4) * (NT + NY) + 2) * sizeof(float);
+  return (size_t)(256 / C) * ((C + 8) * NY + (C + 4) * NT + 2) * sizeof(float);
 }
 // Dynamic LDS of the last layer's 32-channel adjoint: two alternating buffers
 // of the group's dE/dGamma contributions and of its edge centres.
@@ -939,10 +940,16 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
   constexpr int CC = MW >= 0 || MW == -2 ? mix32::C : 0;
   constexpr bool LAST = MW == -2;
   const int C = CC > 0 ? CC : a.C;
-  const int epb = 256 / C, CP = C + 4;
+  // the 32-channel plan stages dE/dV already split into the BF16 operand(s)
+  // of the mixing adjoint (rows of CPH values: hi, then lo gtlo further);
+  // otherwise as FP32 rows of CP floats. The region holds either.
+  constexpr int GS = MW >= 0 && KIND != G_F32 ? (KIND == G_BF16X3 ? 2 : 1) : 0;
+  const int epb = 256 / C, CP = C + 4, CPH = C + 8;
   const int el = threadIdx.x / C, c = threadIdx.x % C, lane = threadIdx.x & 63;
   float* gVl = nq_dyn_lds;
-  float* gTl = nq_dyn_lds + epb * NY * CP;
+  bf16* gVh = reinterpret_cast<bf16*>(nq_dyn_lds);
+  const int gtlo = epb * NY * CPH;  // lo rows after the hi rows
+  float* gTl = nq_dyn_lds + epb * NY * CPH;
   const int64_t ne = *a.nedge_p;
   // groups of epb edges start at multiples of epb of the global edge index
   // (edge e of a chunk is edge e0 + e of the system), so the run sums below
@@ -1005,9 +1012,21 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
       // The previous group's reads of gTl finished before this barrier pair
       // lets the mixing overwrite it.
 #pragma unroll
-      for (int lm = 0; lm < NY; ++lm) gVl[(el * NY + lm) * CP + c] = valid ? gv[lm] : 0.f;
+      for (int lm = 0; lm < NY; ++lm) {
+        const float v = valid ? gv[lm] : 0.f;
+        if constexpr (GS == 0) {
+          gVl[(el * NY + lm) * CP + c] = v;
+        } else {
+          bf16* gr = gVh + (el * NY + lm) * CPH + c;
+          const bf16 h = (bf16)v;
+          gr[0] = h;
+          if constexpr (GS == 2) gr[gtlo] = (bf16)(v - (float)h);
+        }
+      }
       __syncthreads();
-      if constexpr (MW >= 0)
+      if constexpr (GS > 0)
+        mix32::mix_bwd_split<KIND, MW>(B, gVh, gtlo, gTl, lane);
+      else if constexpr (MW >= 0)
         mix32::mix_bwd<KIND, MW>(B, gVl, gTl, lane);
       else
         mix_bwd<KIND, LMAX>(gVl, gTl, epb, C, a.W);
