@@ -238,21 +238,30 @@ nq_status nq_edges_export(nq_ctx* ctx, int32_t* ei, int32_t* ej, int64_t cap, in
 
 /* Copy a named per-edge or per-atom intermediate of the last evaluation into
  * out[cap] (device, FP32) and report its row count and width (host). Names:
- * "geom" (d, u, Y...), "x0", "w0", "gamma<t>", "s<t>", "x<t>", "V<t>", "eij",
- * "g" (dE/dr_ij). For parity tests of single stages. Synchronises the stream. */
+ * "geom" (d, u, Y...), "h0" (two-body input row), "x0", "we1" ([V_0 | w_1]
+ * products), "gamma<t>", "s<t>", "x<t>", "V<t>", "eij", "g" (dE/dr_ij), "gu"
+ * (dE/du), "gY" (dE/dY parts), "gh0" (dE/dh0 in the first 2 S + n_bessel of
+ * its columns). For parity tests of single stages. Synchronises the stream. */
 nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, float* out,
                           int64_t cap, int64_t* rows, int64_t* width);
 
-/* Evaluation path of later calls on this context. NQ_PATH_AUTO (default) and
- * NQ_PATH_LAYERED: the layered kernels (one launch per stage, activations in
- * device memory; the faster path on the benchmark workload, and the one
- * nq_debug_export reads). NQ_PATH_FUSED: one persistent kernel per
+/* Evaluation path of later calls on this context. NQ_PATH_LAYERED: the
+ * layered kernels (one launch per stage and product, activations in device
+ * memory; the path whose products nq_autotune times and whose intermediates
+ * nq_debug_export reads). NQ_PATH_AUTO (default): the same kernels, except
+ * that the two-body MLP runs as one kernel per direction (forward: only its
+ * last pre-activation is stored; adjoint: the first two layers are
+ * recomputed) where that kernel is compiled: two-body widths 64-128-256 on at
+ * most 16 inputs padded to 32, latent width 256, precision BF16 or BF16X3 and
+ * no per-product override of a two-body product. Its results are bitwise those
+ * of NQ_PATH_LAYERED; it is the faster path on the benchmark workload.
+ * NQ_PATH_FUSED: one persistent kernel per
  * evaluation that runs the forward pass and its adjoint centre by centre and
  * keeps the edge activations of each 64-edge block on chip; it is compiled
  * for l <= 2, two layers, 32 channels, two-body MLP 64-128-256, one 256-wide
  * latent layer, a 128-wide edge layer, three species, eight Bessel functions
  * and precision BF16 or BF16X3, and the next evaluation returns
- * NQ_ERR_UNSUPPORTED for other models. Both paths compute the same function
+ * NQ_ERR_UNSUPPORTED for other models. All paths compute the same function
  * (paper Sec. 2.1, Eq. 1) and agree to rounding. NQ_ERR_ARG for other
  * values. Synchronises the stream and drops the captured MD graph. */
 #define NQ_PATH_AUTO 0

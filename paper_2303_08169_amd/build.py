@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libnnqmd.so")
-SOURCES = ["api.hip", "model.hip", "neighbor.hip", "pipeline.hip", "gemm_ws.hip", "md.hip", "fused.hip"]
+SOURCES = ["api.hip", "model.hip", "neighbor.hip", "pipeline.hip", "gemm_ws.hip", "md.hip", "fused.hip", "twobody.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-Wall", "-Wno-unused-function",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

@@ -584,6 +584,7 @@ nq_status nq_debug_export(nq_ctx* ctx, const nq_model* model, const char* name, 
     else if (s == "g") { src = reinterpret_cast<const float*>(ws.gr); w = 4; r = ne_all; }
     else if (s == "gu") { src = ws.gu; w = 1; }
     else if (s == "gY") { src = ws.gY; w = 16 * (d.T + 1); }
+    else if (s == "gh0") { src = ws.gh[0]; w = ws.maxw; }
     else if ((t = layer("gamma")) >= 1 && t <= d.T) { src = ws.gam[t]; w = d.NY * d.C; r = ws.v_n; }
     else if ((t = layer("s")) >= 1 && t <= d.T) { src = ws.s[t]; w = d.nscal * d.C; }
     else if ((t = layer("V")) >= 1 && t < d.T) { src = ws.V[t]; w = d.NY * d.C; }

@@ -278,6 +278,11 @@ void debug_x0_async(nq_ctx* ctx, const nq_model* m, float* out);
 // (NQ_RING_POLYMER_NOALLOC_MAX doubles), looked up once per device; the
 // device must be current.
 double* ring_polymer_static_scratch(int device);
+// The two-body MLP as one kernel per direction (benchmark widths, BF16 kinds,
+// automatic path only); bitwise the per-layer products.
+bool tb_fused(const nq_ctx* ctx, const nq_model* m);
+void tb_fwd_async(nq_ctx* ctx, const nq_model* m);
+void tb_bwd_async(nq_ctx* ctx, const nq_model* m);
 
 // Arithmetic of one product site: its override, else the model's precision.
 inline int site_precision(const nq_model* m, const std::string& site) {

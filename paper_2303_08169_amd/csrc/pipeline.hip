@@ -1841,7 +1841,9 @@ void forward_async(nq_ctx* ctx, const nq_model* m, const int32_t* species, doubl
   // two-body MLP; x0 = u * SiLU(a) of the last layer is not stored: its two
   // readers (the [w0 | e1] product and the first latent layer, operand and
   // residual) form it from the stored pre-activation a
-  for (int k = 0; k < d.n_tb; ++k) {
+  const bool tb1 = tb_fused(ctx, m);
+  if (tb1) tb_fwd_async(ctx, m);
+  for (int k = 0; k < d.n_tb && !tb1; ++k) {
     const Lin& L = *m->tb[k];
     ALoad ld = k == 0 ? a_plain(ws.h0, ws.K0p, ws.K0p) : a_silu(ws.a_tb[k - 1], d.tb[k - 1], d.tb[k - 1]);
     gemm(ctx, m, L, false, ld, e_store(ws.a_tb[k], d.tb[k], d.tb[k]), "fwd.twobody." + std::to_string(k));
@@ -1964,7 +1966,12 @@ void backward_async(nq_ctx* ctx, const nq_model* m) {
   // two-body MLP: x0 = u SiLU(a_last)
   const int kt = d.n_tb - 1;
   float* gout = nullptr;
-  for (int k = kt; k >= 0; --k) {
+  const bool tb1 = tb_fused(ctx, m);
+  if (tb1) {
+    tb_bwd_async(ctx, m);
+    gout = ws.gh[0];
+  }
+  for (int k = kt; k >= 0 && !tb1; --k) {
     // the first product also adds dE/du of x0 = u SiLU(a) to gu
     ALoad ld = k == kt ? a_gradsilu(ws.gx, d.D, d.tb[k], ws.a_tb[k], d.tb[k], u, 1.f, ws.gu)
                        : a_gradsilu(gout, ws.maxw, d.tb[k], ws.a_tb[k], d.tb[k], nullptr, 1.f);
