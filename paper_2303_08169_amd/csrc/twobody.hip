@@ -172,18 +172,21 @@ __device__ inline void put_h0(bf16* A0, const float4& v, bool ok, int tid) {
 // Output element q of a 16 x 16 product tile: row 4 (lane / 16) + q, column lane % 16.
 __device__ inline int orow(int lane, int q) { return 4 * (lane / 16) + q; }
 
-// Wavefront w's share of the first two layers: a0 of column tile w % 4 and
-// row tile w / 4 (s0 = SiLU(a0) into S0), barrier, a1 of column tile w and
-// both row tiles (into S1 as s1 = SiLU(a1) when S1 is given). The FP32
-// pre-activations stay in a0 and a1.
+// Wavefront w's part of the first layer: a0 of column tile w % 4 and row
+// tile w / 4, kept in a0; s0 = SiLU(a0) split into S0.
 template <int KIND>
-__device__ inline void layers01(const bf16* A0, const bf16* W0s, const bf16* W1s, bf16* S0, bf16* S1, int wave,
-                                int lane, floatx4 (&a0)[1], floatx4 (&a1)[2]) {
+__device__ inline void layer0(const bf16* A0, const bf16* W0s, bf16* S0, int wave, int lane, floatx4 (&a0)[1]) {
   const int rt = wave / 4, c0 = (wave % 4) * 16;
   mma_lds<KIND, K0 / 32, 1>(A0 + rt * 16 * L0, L0, RT * L0, W0s, L0, N0 * L0, c0, lane, a0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q) put_split<KIND>(S0, RT * L1, (rt * 16 + orow(lane, q)) * L1 + c0 + lane % 16, siluf(a0[0][q]));
-  __syncthreads();
+  for (int q = 0; q < 4; ++q)
+    put_split<KIND>(S0, RT * L1, (rt * 16 + orow(lane, q)) * L1 + c0 + lane % 16, siluf(a0[0][q]));
+}
+
+// Wavefront w's part of the second layer: a1 of column tile w, both row
+// tiles, kept in a1; with S1 given, s1 = SiLU(a1) split into it.
+template <int KIND>
+__device__ inline void layer1(const bf16* S0, const bf16* W1s, bf16* S1, int wave, int lane, floatx4 (&a1)[2]) {
   mma_lds<KIND, N0 / 32, 2>(S0, L1, RT * L1, W1s, L1, N1 * L1, wave * 16, lane, a1);
   if (S1) {
 #pragma unroll
@@ -194,6 +197,14 @@ __device__ inline void layers01(const bf16* A0, const bf16* W0s, const bf16* W1s
   }
 }
 
+// The workgroups take tiles blockIdx.x, + gridDim.x, ... Both kernels are
+// software-pipelined over a workgroup's tiles so that independent products of
+// consecutive tiles share the phases between two barriers.
+
+// Forward, per tile i: phase 1 = layer 0 of tile i and the last layer's first
+// column half of tile i - 1; phase 2 = layer 1 of tile i (into S1 buffer
+// i % 2), the second column half of tile i - 1 and the input rows of tile
+// i + 1 into A0. A final pass of both phases ends tile i - 1 alone.
 template <int KIND>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tb_fwd(Args a) {
   constexpr int H = KIND == G_BF16X3 ? 2 : 1;
@@ -201,9 +212,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ __attribute__((aligned(16))) bf16 W1s[H * N1 * L1];
   __shared__ __attribute__((aligned(16))) bf16 A0[H * RT * L0];
   __shared__ __attribute__((aligned(16))) bf16 S0[H * RT * L1];
-  __shared__ __attribute__((aligned(16))) bf16 S1[H * RT * L2];
+  __shared__ __attribute__((aligned(16))) bf16 S1[2][H * RT * L2];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int64_t nrows = *a.nrows, ntiles = (nrows + RT - 1) / RT;
+  const int64_t nrows = *a.nrows, ntiles = (nrows + RT - 1) / RT, G = gridDim.x;
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
   stage_w(W0s, a.w0, N0, K0, L0, H, tid);
@@ -212,35 +223,50 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   bf16x8 bw[2][N1 / 32][H];
   load_frags(bw[0], a.w2, N2, N1, 32 * wave, lane);
   load_frags(bw[1], a.w2, N2, N1, 32 * wave + 16, lane);
+  auto clampt = [&](int64_t t) { return t < ntiles ? t : ntiles - 1; };
   float4 hv = load_h0(a, tile, nrows, tid & 255);
-  for (; tile < ntiles; tile += gridDim.x) {
-    const int64_t row0 = tile * RT;
+  if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tile * RT + tid / (K0 / 4) < nrows, tid);
+  hv = load_h0(a, clampt(tile + G), nrows, tid & 255);
+  __syncthreads();
+  // a2 = s1 W2 of tile t, column half j (from S1 buffer b), stored
+  auto last_layer = [&](int64_t t, int j, const bf16* s1) {
+    const int64_t row0 = t * RT;
     const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
-    if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tid / (K0 / 4) < nvalid, tid);
-    const int64_t next = tile + gridDim.x;
-    hv = load_h0(a, next < ntiles ? next : ntiles - 1, nrows, tid & 255);
-    __syncthreads();
-    floatx4 a0[1], a1[2];
-    layers01<KIND>(A0, W0s, W1s, S0, S1, wave, lane, a0, a1);
-    __syncthreads();
-    // a2 = s1 W2, stored as the forward output
     const __amdgpu_buffer_rsrc_t R = buffer_rsrc(a.a2 + row0 * N2, nvalid * N2 * 4);
+    floatx4 acc[2];
+    mma_reg<KIND, N1 / 32, 2, H>(s1, L2, RT * L2, bw[j], lane, acc);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) {
-      floatx4 acc[2];
-      mma_reg<KIND, N1 / 32, 2, H>(S1, L2, RT * L2, bw[j], lane, acc);
+    for (int i = 0; i < 2; ++i)
 #pragma unroll
-      for (int i = 0; i < 2; ++i)
-#pragma unroll
-        for (int q = 0; q < 4; ++q)
-          buf_store(acc[i][q], R, (unsigned)((i * 16 + orow(lane, q)) * N2 + 32 * wave + 16 * j + lane % 16) * 4);
+      for (int q = 0; q < 4; ++q)
+        buf_store(acc[i][q], R, (unsigned)((i * 16 + orow(lane, q)) * N2 + 32 * wave + 16 * j + lane % 16) * 4);
+  };
+  int64_t prev = -1;
+  for (int it = 0;; ++it) {
+    const bool cur = tile < ntiles;  // uniform
+    floatx4 a0[1], a1[2];
+    if (cur) layer0<KIND>(A0, W0s, S0, wave, lane, a0);
+    if (prev >= 0) last_layer(prev, 0, S1[(it + 1) & 1]);
+    __syncthreads();
+    if (cur) layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
+    if (prev >= 0) last_layer(prev, 1, S1[(it + 1) & 1]);
+    const int64_t next = tile + G;
+    if (next < ntiles) {
+      if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
+      hv = load_h0(a, clampt(next + G), nrows, tid & 255);
     }
-    // A0 and S0 were last read before the barrier above; S1 is written again
-    // only after the next tile's first barrier, which every wavefront reaches
-    // after its reads here
+    __syncthreads();
+    if (!cur) break;
+    prev = tile;
+    tile = next;
   }
 }
 
+// Adjoint, per tile i: phase 1 = dE/da2 and dE/du of tile i and dE/dh0 of
+// tile i - 1 (wavefronts 0 and 1); phase 2 = a1 of tile i recomputed
+// (registers) and dE/ds1 -> dE/da1 into G1, the input rows of tile i + 1
+// into A0; phase 3 = dE/ds0 -> dE/da0 of tile i into G0 and a0 of tile i + 1
+// recomputed (registers, s0 into S0). A last phase 1 ends tile i - 1 alone.
 template <int KIND>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tb_bwd(Args a) {
   constexpr int H = KIND == G_BF16X3 ? 2 : 1;
@@ -253,7 +279,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ __attribute__((aligned(16))) bf16 G1[H * RT * L2];    // dE/da1 (split)
   __shared__ __attribute__((aligned(16))) bf16 G0[H * RT * L1];    // dE/da0 (split)
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
-  const int64_t nrows = *a.nrows, ntiles = (nrows + RT - 1) / RT;
+  const int64_t nrows = *a.nrows, ntiles = (nrows + RT - 1) / RT, G = gridDim.x;
   int64_t tile = blockIdx.x;
   if (tile >= ntiles) return;
   stage_w(W0s, a.w0, N0, K0, L0, H, tid);
@@ -264,6 +290,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   bf16x8 bw[N2 / 32][H], b0w[N0 / 32][H];
   load_frags(bw, a.b2, N1, N2, 16 * wave, lane);
   load_frags(b0w, a.b0, 16, N0, 0, lane);
+  auto clampt = [&](int64_t t) { return t < ntiles ? t : ntiles - 1; };
   // dE/da2 inputs: wavefront w holds rows w + 8 q (q < 4), lane l their
   // 4-chunk l (columns 4 l .. 4 l + 3: K step l / 8, position l % 8 in it)
   float4 gv[4], av[4];
@@ -279,43 +306,66 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       guv[q] = a.gu[row];
     }
   };
-  float4 hv = load_h0(a, tile, nrows, tid & 255);
+  // dE/dh0 = dE/da0 W0^T of tile t (wavefronts 0 and 1: row tile w), the first n_in columns stored
+  auto first_layer_adjoint = [&](int64_t t) {
+    if (wave < 2) {
+      const int64_t row0 = t * RT;
+      const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+      floatx4 acc[1];
+      mma_reg<KIND, N0 / 32, 1, H>(G0 + wave * 16 * L1, L1, RT * L1, b0w, lane, acc);
+      const __amdgpu_buffer_rsrc_t R = buffer_rsrc(a.gh0 + row0 * a.ldgh, nvalid * a.ldgh * 4);
+      const int c = lane % 16;
+#pragma unroll
+      for (int q = 0; q < 4; ++q)
+        buf_store(acc[0][q], R, c < a.n_in ? (unsigned)((wave * 16 + orow(lane, q)) * a.ldgh + c) * 4 : kOutOfRange);
+    }
+  };
   load_g(tile);
-  for (; tile < ntiles; tile += gridDim.x) {
+  float4 hv = load_h0(a, tile, nrows, tid & 255);
+  if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tile * RT + tid / (K0 / 4) < nrows, tid);
+  hv = load_h0(a, clampt(tile + G), nrows, tid & 255);
+  __syncthreads();
+  floatx4 a0[1];  // a0 of the current tile (column tile w % 4, row tile w / 4)
+  layer0<KIND>(A0, W0s, S0, wave, lane, a0);
+  __syncthreads();
+  int64_t prev = -1;
+  for (;;) {
+    const bool cur = tile < ntiles;  // uniform
+    const int64_t next = tile + G;
     const int64_t row0 = tile * RT;
     const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
-    if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tid / (K0 / 4) < nvalid, tid);
-    // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2): each row's
-    // 4-chunk shares summed per position over the K steps in order, then the
-    // 8 positions pairwise (the per-layer kernels' order), across lanes
+    if (cur) {
+      // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2): each
+      // row's 4-chunk shares summed per position over the K steps in order,
+      // then the 8 positions pairwise (the per-layer kernels' order), across lanes
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int r = wave + 8 * q;
-      const bool ok = r < nvalid;
-      const float4 g4 = gv[q], a4 = av[q];
-      const float sx = sigmoidf_(a4.x), sy = sigmoidf_(a4.y), sz = sigmoidf_(a4.z), sw = sigmoidf_(a4.w);
-      const float e[4] = {ok ? gradsilu_scale(g4.x, a4.x, sx, uv[q]) : 0.f, ok ? gradsilu_scale(g4.y, a4.y, sy, uv[q]) : 0.f,
-                          ok ? gradsilu_scale(g4.z, a4.z, sz, uv[q]) : 0.f, ok ? gradsilu_scale(g4.w, a4.w, sw, uv[q]) : 0.f};
-      put_split4<KIND>(G2, RT * LG, r * LG + 4 * lane, e);
-      const float part = ok ? gradsilu_part(g4, a4, sx, sy, sz, sw) : 0.f;
-      float rj = 0.f;
+      for (int q = 0; q < 4; ++q) {
+        const int r = wave + 8 * q;
+        const bool ok = r < nvalid;
+        const float4 g4 = gv[q], a4 = av[q];
+        const float sx = sigmoidf_(a4.x), sy = sigmoidf_(a4.y), sz = sigmoidf_(a4.z), sw = sigmoidf_(a4.w);
+        const float e[4] = {ok ? gradsilu_scale(g4.x, a4.x, sx, uv[q]) : 0.f, ok ? gradsilu_scale(g4.y, a4.y, sy, uv[q]) : 0.f,
+                            ok ? gradsilu_scale(g4.z, a4.z, sz, uv[q]) : 0.f, ok ? gradsilu_scale(g4.w, a4.w, sw, uv[q]) : 0.f};
+        put_split4<KIND>(G2, RT * LG, r * LG + 4 * lane, e);
+        const float part = ok ? gradsilu_part(g4, a4, sx, sy, sz, sw) : 0.f;
+        float rj = 0.f;
 #pragma unroll
-      for (int s2 = 0; s2 < 8; ++s2) rj += __shfl(part, 8 * s2 + (lane & 7));
-      rj += __shfl_xor(rj, 1);
-      rj += __shfl_xor(rj, 2);
-      rj += __shfl_xor(rj, 4);
-      if (ok && lane == 0) a.gu[row0 + r] = guv[q] + 1.f * rj;
+        for (int s2 = 0; s2 < 8; ++s2) rj += __shfl(part, 8 * s2 + (lane & 7));
+        rj += __shfl_xor(rj, 1);
+        rj += __shfl_xor(rj, 2);
+        rj += __shfl_xor(rj, 4);
+        if (ok && lane == 0) a.gu[row0 + r] = guv[q] + 1.f * rj;
+      }
+      load_g(clampt(next));
     }
-    const int64_t next = tile + gridDim.x;
-    hv = load_h0(a, next < ntiles ? next : ntiles - 1, nrows, tid & 255);
-    load_g(next < ntiles ? next : ntiles - 1);
+    if (prev >= 0) first_layer_adjoint(prev);
     __syncthreads();
-    // a0, a1 again from h0 (kept in registers where dE/da0, dE/da1 need them)
-    floatx4 a0[1], a1[2];
-    layers01<KIND>(A0, W0s, W1s, S0, nullptr, wave, lane, a0, a1);
-    // dE/ds1 = dE/da2 W2^T (column tile w, both row tiles), then dE/da1 = dE/ds1 SiLU'(a1)
+    if (!cur) break;
+    // a1 again (registers), then dE/ds1 = dE/da2 W2^T (column tile w, both
+    // row tiles) and dE/da1 = dE/ds1 SiLU'(a1) into G1
     {
-      floatx4 acc[2];
+      floatx4 a1[2], acc[2];
+      layer1<KIND>(S0, W1s, nullptr, wave, lane, a1);
       mma_reg<KIND, N2 / 32, 2, H>(G2, LG, RT * LG, bw, lane, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
@@ -327,8 +377,13 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                           r < nvalid ? gradsilu_scale(acc[i][q], x, sigmoidf_(x), 1.f) : 0.f);
         }
     }
+    if (next < ntiles) {
+      if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
+      hv = load_h0(a, clampt(next + G), nrows, tid & 255);
+    }
     __syncthreads();
-    // dE/ds0 = dE/da1 W1^T (column tile w % 4, row tile w / 4), then dE/da0 = dE/ds0 SiLU'(a0)
+    // dE/ds0 = dE/da1 W1^T (column tile w % 4, row tile w / 4), then
+    // dE/da0 = dE/ds0 SiLU'(a0) into G0; a0 of the next tile
     {
       const int rt = wave / 4, c0 = (wave % 4) * 16;
       floatx4 acc[1];
@@ -341,20 +396,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                         r < nvalid ? gradsilu_scale(acc[0][q], x, sigmoidf_(x), 1.f) : 0.f);
       }
     }
+    if (next < ntiles) layer0<KIND>(A0, W0s, S0, wave, lane, a0);
     __syncthreads();
-    // dE/dh0 = dE/da0 W0^T (wavefronts 0 and 1: row tile w), the first n_in columns stored
-    if (wave < 2) {
-      floatx4 acc[1];
-      mma_reg<KIND, N0 / 32, 1, H>(G0 + wave * 16 * L1, L1, RT * L1, b0w, lane, acc);
-      const __amdgpu_buffer_rsrc_t R = buffer_rsrc(a.gh0 + row0 * a.ldgh, nvalid * a.ldgh * 4);
-      const int c = lane % 16;
-#pragma unroll
-      for (int q = 0; q < 4; ++q)
-        buf_store(acc[0][q], R, c < a.n_in ? (unsigned)((wave * 16 + orow(lane, q)) * a.ldgh + c) * 4 : kOutOfRange);
-    }
-    // A0, G2 (last read before the second barrier above) and S0, G1, G0
-    // (read before the third and fourth) are rewritten only after the next
-    // tile's first barrier
+    prev = tile;
+    tile = next;
   }
 }
 

@@ -39,6 +39,8 @@ SPAN_KERNELS = [
     (r"^edge_list$", ("k_edge_count",)),
     (r"^chunk_view$", ("k_chunk_edges",)),
     (r"^geometry$", ("k_geometry",)),
+    (r"^fwd\.twobody$", ("k_tb_fwd",)),
+    (r"^bwd\.twobody$", ("k_tb_bwd",)),
     (r"^(fwd|bwd)\.", ("k_gemm", "k_gemm_ws")),
     (r"^tp_fwd\d+$", ("k_tp_fwd", "k_tp_fwd_last32")),
     (r"^tp_bwd\d+$", ("k_tp_bwd", "k_tp_bwd_last32")),

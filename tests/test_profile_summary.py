@@ -144,3 +144,12 @@ def test_chunked_evaluations_are_keyed_by_kernel(tmp_path):
     assert k["k_gemm_ws"]["hbm_bytes_per_launch"] == pytest.approx(1024 * (50 * 2 + 100))
     per_eval = sum(v for _, v in EVAL)
     assert rec["hbm_bytes_per_step"] == pytest.approx(1024 * (per_eval * 2 + 2 * per_eval))
+
+
+def test_span_kernel_names():
+    assert ps.span_kernels("fwd.twobody") == ("k_tb_fwd",)
+    assert ps.span_kernels("bwd.twobody") == ("k_tb_bwd",)
+    assert ps.span_kernels("fwd.twobody.0") == ("k_gemm", "k_gemm_ws")
+    assert ps.span_kernels("tp_bwd1") == ("k_tp_bwd", "k_tp_bwd_last32")
+    with pytest.raises(ValueError):
+        ps.span_kernels("no_such_span")
