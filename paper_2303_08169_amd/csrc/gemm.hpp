@@ -124,6 +124,38 @@ struct ALoad {
   }
 };
 
+// The dE/du row sum of a 256-wide A row whose 64 four-value chunks are held
+// one per lane of a wavefront (lane l: chunk l = 8 s + j, K step s, position
+// j in it): per position the shares of K steps 0..7 in order, then the 8
+// positions pairwise; every product kernel adds in this order. Done with
+// cross-lane register moves (DPP row shifts and quad permutes, row and half
+// swaps) instead of LDS round trips; the result is in lane 0.
+template <int CTRL>
+__device__ inline float dpp_f(float v) {
+  return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xf, 0xf, false));
+}
+__device__ inline float row_share_sum(float x) {
+  constexpr int kShl8 = 0x108, kShl4 = 0x104, kSwap1 = 0xB1, kSwap2 = 0x4E;  // row_shl:8, row_shl:4, quad_perm
+  const unsigned xi = __float_as_uint(x);
+  // y: lane j holds the share of lane j + 16; z: of lane j + 32; w: of lane j + 48
+  const float y = __uint_as_float(__builtin_amdgcn_permlane16_swap(xi, xi, false, false)[1]);
+  const unsigned zi = __builtin_amdgcn_permlane32_swap(xi, xi, false, false)[1];
+  const float z = __uint_as_float(zi);
+  const float w = __uint_as_float(__builtin_amdgcn_permlane16_swap(zi, zi, false, false)[1]);
+  float s = 0.f + x;
+  s += dpp_f<kShl8>(x);
+  s += y;
+  s += dpp_f<kShl8>(y);
+  s += z;
+  s += dpp_f<kShl8>(z);
+  s += w;
+  s += dpp_f<kShl8>(w);
+  s += dpp_f<kSwap1>(s);
+  s += dpp_f<kSwap2>(s);
+  s += dpp_f<kShl4>(s);
+  return s;
+}
+
 enum EpiMode { E_STORE = 0, E_STORE_X0 = 1, E_RESIDUAL = 2, E_LATENT_BWD = 3, E_ADD = 4 };
 
 struct Epi {
@@ -502,7 +534,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   __shared__ __attribute__((aligned(16))) float Os[EPI == 1 ? RT * LDO : 4];
   constexpr bool ADD = EMODE == E_ADD && EPI == 1;  // the accumulated rows are staged like A
   constexpr bool GU = GR && KS == 8;  // dE/du row sums (the launcher passes gu only when Kp = 256)
-  __shared__ float Rd[GU ? 2 : 1][GU ? RT * 64 : 4];
+  __shared__ float Rs[GU ? 2 : 1][GU ? RT : 4];  // dE/du row sums of the staged tile
   __shared__ __attribute__((aligned(16))) float Is[ADD ? 2 : 1][ADD ? RT * LDO : 4];
   const int tid = threadIdx.x, wave = tid / 64, lane = tid % 64;
   const int64_t nrows = *nrows_p;
@@ -639,9 +671,12 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         *reinterpret_cast<bf16x4*>(&dst[rr * LDH + k]) = hi;
         if constexpr (H == 2) *reinterpret_cast<bf16x4*>(&dst[RT * LDH + rr * LDH + k]) = lo;
       }
-      // the row's chunk shares of dE/du, in chunk order (a wavefront's 64
-      // lanes hold one row: Kp = 256); the tile's iteration adds them up
-      if constexpr (GU) Rd[it1][rr * 64 + lane] = rd;
+      // the row's dE/du sum (a wavefront's 64 lanes hold one row: Kp = 256),
+      // added to dE/du by the tile's iteration
+      if constexpr (GU) {
+        const float sum = row_share_sum(rd);
+        if (lane == 0) Rs[it1][rr] = sum;
+      }
     }
   };
 
@@ -680,22 +715,13 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
     }
     if constexpr (GU) {
-      // dE/du of the tile's rows (staged with the tile): row t's 64 chunk
-      // shares summed as k_gemm sums them (per 8-chunk group sequentially
-      // over the 8 K steps, then pairwise across the groups), so dE/du is
-      // bitwise identical too; the store is unconditional (dropped for t >= 16)
+      // dE/du of the tile's rows: row t's sum (formed when the tile was
+      // staged, in k_gemm's order, so dE/du is bitwise identical too) added
+      // to the staged dE/du; the store is unconditional (dropped for t >= 16)
       float val = 0.f;
       unsigned off = kOutOfRange;
       if (t < RT) {
-        const float* rp = Rd[it & 1] + t * 64;
-        float r[8];
-#pragma unroll
-        for (int j = 0; j < 8; ++j) r[j] = 0.f;
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2)
-#pragma unroll
-          for (int j = 0; j < 8; ++j) r[j] += rp[s2 * 8 + j];
-        val = Us[it & 1][t] + ld.c * (((r[0] + r[1]) + (r[2] + r[3])) + ((r[4] + r[5]) + (r[6] + r[7])));
+        val = Us[it & 1][t] + ld.c * Rs[it & 1][t];
         off = (unsigned)t * 4;
       }
       buf_store(val, gu_rsrc(tile * RT), off);

@@ -335,9 +335,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int64_t row0 = tile * RT;
     const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
     if (cur) {
-      // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2): each
-      // row's 4-chunk shares summed per position over the K steps in order,
-      // then the 8 positions pairwise (the per-layer kernels' order), across lanes
+      // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2) in the
+      // per-layer kernels' order
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = wave + 8 * q;
@@ -347,13 +346,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         const float e[4] = {ok ? gradsilu_scale(g4.x, a4.x, sx, uv[q]) : 0.f, ok ? gradsilu_scale(g4.y, a4.y, sy, uv[q]) : 0.f,
                             ok ? gradsilu_scale(g4.z, a4.z, sz, uv[q]) : 0.f, ok ? gradsilu_scale(g4.w, a4.w, sw, uv[q]) : 0.f};
         put_split4<KIND>(G2, RT * LG, r * LG + 4 * lane, e);
-        const float part = ok ? gradsilu_part(g4, a4, sx, sy, sz, sw) : 0.f;
-        float rj = 0.f;
-#pragma unroll
-        for (int s2 = 0; s2 < 8; ++s2) rj += __shfl(part, 8 * s2 + (lane & 7));
-        rj += __shfl_xor(rj, 1);
-        rj += __shfl_xor(rj, 2);
-        rj += __shfl_xor(rj, 4);
+        const float rj = row_share_sum(ok ? gradsilu_part(g4, a4, sx, sy, sz, sw) : 0.f);
         if (ok && lane == 0) a.gu[row0 + r] = guv[q] + 1.f * rj;
       }
       load_g(clampt(next));
