@@ -173,14 +173,18 @@ __device__ inline void put_h0(bf16* A0, const float4& v, bool ok, int tid) {
 __device__ inline int orow(int lane, int q) { return 4 * (lane / 16) + q; }
 
 // Wavefront w's part of the first layer: a0 of column tile w % 4 and row
-// tile w / 4, kept in a0; s0 = SiLU(a0) split into S0.
+// tile w / 4, kept in a0 with its sigmoid in sg0 (SiLU(a) = a sigmoid(a));
+// s0 = SiLU(a0) split into S0.
 template <int KIND>
-__device__ inline void layer0(const bf16* A0, const bf16* W0s, bf16* S0, int wave, int lane, floatx4 (&a0)[1]) {
+__device__ inline void layer0(const bf16* A0, const bf16* W0s, bf16* S0, int wave, int lane, floatx4 (&a0)[1],
+                              floatx4& sg0) {
   const int rt = wave / 4, c0 = (wave % 4) * 16;
   mma_lds<KIND, K0 / 32, 1>(A0 + rt * 16 * L0, L0, RT * L0, W0s, L0, N0 * L0, c0, lane, a0);
 #pragma unroll
-  for (int q = 0; q < 4; ++q)
-    put_split<KIND>(S0, RT * L1, (rt * 16 + orow(lane, q)) * L1 + c0 + lane % 16, siluf(a0[0][q]));
+  for (int q = 0; q < 4; ++q) {
+    sg0[q] = sigmoidf_(a0[0][q]);
+    put_split<KIND>(S0, RT * L1, (rt * 16 + orow(lane, q)) * L1 + c0 + lane % 16, a0[0][q] * sg0[q]);
+  }
 }
 
 // Wavefront w's part of the second layer: a1 of column tile w, both row
@@ -244,8 +248,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   int64_t prev = -1;
   for (int it = 0;; ++it) {
     const bool cur = tile < ntiles;  // uniform
-    floatx4 a0[1], a1[2];
-    if (cur) layer0<KIND>(A0, W0s, S0, wave, lane, a0);
+    floatx4 a0[1], a1[2], sg0;
+    if (cur) layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
     if (prev >= 0) last_layer(prev, 0, S1[(it + 1) & 1]);
     __syncthreads();
     if (cur) layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
@@ -325,8 +329,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tile * RT + tid / (K0 / 4) < nrows, tid);
   hv = load_h0(a, clampt(tile + G), nrows, tid & 255);
   __syncthreads();
-  floatx4 a0[1];  // a0 of the current tile (column tile w % 4, row tile w / 4)
-  layer0<KIND>(A0, W0s, S0, wave, lane, a0);
+  floatx4 a0[1], sg0;  // a0 of the current tile (column tile w % 4, row tile w / 4), its sigmoid
+  layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
   __syncthreads();
   int64_t prev = -1;
   for (;;) {
@@ -384,12 +388,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = rt * 16 + orow(lane, q);
-        const float x = a0[0][q];
         put_split<KIND>(G0, RT * L1, r * L1 + c0 + lane % 16,
-                        r < nvalid ? gradsilu_scale(acc[0][q], x, sigmoidf_(x), 1.f) : 0.f);
+                        r < nvalid ? gradsilu_scale(acc[0][q], a0[0][q], sg0[q], 1.f) : 0.f);
       }
     }
-    if (next < ntiles) layer0<KIND>(A0, W0s, S0, wave, lane, a0);
+    if (next < ntiles) layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
     __syncthreads();
     prev = tile;
     tile = next;
