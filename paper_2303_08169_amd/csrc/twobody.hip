@@ -205,10 +205,10 @@ __device__ inline void layer1(const bf16* S0, const bf16* W1s, bf16* S1, int wav
 // software-pipelined over a workgroup's tiles so that independent products of
 // consecutive tiles share the phases between two barriers.
 
-// Forward, per tile i: phase 1 = layer 0 of tile i and the last layer's first
-// column half of tile i - 1; phase 2 = layer 1 of tile i (into S1 buffer
-// i % 2), the second column half of tile i - 1 and the input rows of tile
-// i + 1 into A0. A final pass of both phases ends tile i - 1 alone.
+// Forward, per tile i: phase 1 = layer 0 of tile i and the last layer of
+// tile i - 1 (four independent accumulation chains per wavefront); phase 2 =
+// layer 1 of tile i (into S1 buffer i % 2) and the input rows of tile i + 1
+// into A0. A final pass of both phases ends tile i - 1 alone.
 template <int KIND>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tb_fwd(Args a) {
   constexpr int H = KIND == G_BF16X3 ? 2 : 1;
@@ -250,10 +250,12 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const bool cur = tile < ntiles;  // uniform
     floatx4 a0[1], a1[2], sg0;
     if (cur) layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
-    if (prev >= 0) last_layer(prev, 0, S1[(it + 1) & 1]);
+    if (prev >= 0) {
+      last_layer(prev, 0, S1[(it + 1) & 1]);
+      last_layer(prev, 1, S1[(it + 1) & 1]);
+    }
     __syncthreads();
     if (cur) layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
-    if (prev >= 0) last_layer(prev, 1, S1[(it + 1) & 1]);
     const int64_t next = tile + G;
     if (next < ntiles) {
       if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
