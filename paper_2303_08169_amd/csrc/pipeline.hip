@@ -1004,7 +1004,7 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
     const int par = mixing ? 0 : (it & 1);
     float* const red = redbase + par * epb * NY * CP;
     int* const cent = centbase + par * epb;
-    const int64_t e0 = grp * epb - sh, e = e0 + el;
+    const int64_t e0 = grp * epb - sh;
     // valid rows of the group: lo .. hi - 1 (lo > 0 only in the first group)
     const int lo = e0 < 0 ? (int)-e0 : 0, hi = (int)(ne - e0 < epb ? ne - e0 : epb);
     const bool valid = el >= lo && el < hi;
@@ -1041,24 +1041,25 @@ __device__ inline void tp_bwd_loop(const TpBwdArgs& a) {
       tp_bwd_edge<LMAX, CC>(a, e0, lo, hi, el, c, gTl + el * NT * CP, CP, in, red + el * rstride);
     if (c == 0) cent[el] = cur;
     tp_lds_barrier();
-    if (valid && (el == lo || cent[el] != cent[el - 1])) {
-      float sum[NY];
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) sum[lm] = red[el * rstride + lm * CP + c];
-      // next row's centre and values read together (one LDS round trip per
-      // row); centres are sorted, so the first row of another centre ends the run
-      for (int e2 = el + 1; e2 < hi; ++e2) {
-        const int ce = cent[e2];
-        float v[NY];
-#pragma unroll
-        for (int lm = 0; lm < NY; ++lm) v[lm] = red[e2 * rstride + lm * CP + c];
-        if (ce != cur) break;
-#pragma unroll
-        for (int lm = 0; lm < NY; ++lm) sum[lm] += v[lm];
+    // Run sums, shared by the whole workgroup: for each run of equal centres
+    // (centres are sorted) every thread takes (component, channel) sums of
+    // the run's rows, each added in row order, and stores them at the run's
+    // first row (one thread per run start serialised the group otherwise)
+    // bit k of `starts`: row k begins a run (the same in every wavefront)
+    const int lc = lane < epb ? lane : 0;
+    uint64_t starts = __ballot(lane >= lo && lane < hi && (lane == lo || cent[lc] != cent[lc > 0 ? lc - 1 : 0]));
+    while (starts) {
+      const int k = __builtin_ctzll(starts);
+      starts &= starts - 1;
+      const int end = starts ? __builtin_ctzll(starts) : hi;
+      for (int idx = threadIdx.x; idx < NY * C; idx += 256) {
+        const int lm = idx / C, cc = idx - lm * C;
+        const float* rp = red + k * rstride + lm * CP + cc;
+        float sum = rp[0];
+#pragma unroll 4
+        for (int e2 = 1; e2 < end - k; ++e2) sum += rp[e2 * rstride];
+        a.ggc[(e0 + k) * (NY * C) + idx] = sum;
       }
-      float* ggr = a.ggc + e * (NY * C) + c;
-#pragma unroll
-      for (int lm = 0; lm < NY; ++lm) ggr[lm * C] = sum[lm];
     }
     // The next group's loads go into the same registers once this group's
     // adjoint is done: their latency then overlaps the next group's staging
