@@ -232,10 +232,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tile * RT + tid / (K0 / 4) < nrows, tid);
   hv = load_h0(a, clampt(tile + G), nrows, tid & 255);
   __syncthreads();
-  // a2 = s1 W2 of tile t, column half j (from S1 buffer b), stored
+  // a2 = s1 W2 of tile t, column half j (from S1 buffer b), stored; t < 0
+  // stores nothing (a buffer of no rows)
   auto last_layer = [&](int64_t t, int j, const bf16* s1) {
-    const int64_t row0 = t * RT;
-    const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+    const int64_t row0 = t < 0 ? 0 : t * RT;
+    const int nvalid = t < 0 ? 0 : (int)(nrows - row0 < RT ? nrows - row0 : RT);
     const __amdgpu_buffer_rsrc_t R = buffer_rsrc(a.a2 + row0 * N2, nvalid * N2 * 4);
     floatx4 acc[2];
     mma_reg<KIND, N1 / 32, 2, H>(s1, L2, RT * L2, bw[j], lane, acc);
@@ -249,11 +250,12 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   for (int it = 0;; ++it) {
     const bool cur = tile < ntiles;  // uniform
     floatx4 a0[1], a1[2], sg0;
-    if (cur) layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
-    if (prev >= 0) {
-      last_layer(prev, 0, S1[(it + 1) & 1]);
-      last_layer(prev, 1, S1[(it + 1) & 1]);
-    }
+    // branch-free, so that the two interleave: on the last pass layer 0 works
+    // on a stale input tile whose s0 is never read, on the first the last
+    // layer on an unset S1 buffer and stores nothing
+    layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
+    last_layer(prev, 0, S1[(it + 1) & 1]);
+    last_layer(prev, 1, S1[(it + 1) & 1]);
     __syncthreads();
     if (cur) layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
     const int64_t next = tile + G;
@@ -394,7 +396,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                         r < nvalid ? gradsilu_scale(acc[0][q], a0[0][q], sg0[q], 1.f) : 0.f);
       }
     }
-    if (next < ntiles) layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
+    // (after the last tile: a stale input tile, whose a0 and s0 are never used)
+    layer0<KIND>(A0, W0s, S0, wave, lane, a0, sg0);
     __syncthreads();
     prev = tile;
     tile = next;
