@@ -257,12 +257,11 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     last_layer(prev, 0, S1[(it + 1) & 1]);
     last_layer(prev, 1, S1[(it + 1) & 1]);
     __syncthreads();
-    if (cur) layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
+    layer1<KIND>(S0, W1s, S1[it & 1], wave, lane, a1);
     const int64_t next = tile + G;
-    if (next < ntiles) {
-      if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
-      hv = load_h0(a, clampt(next + G), nrows, tid & 255);
-    }
+    // (past the last tile: zero rows into A0, for the stale last pass)
+    if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
+    hv = load_h0(a, clampt(next + G), nrows, tid & 255);
     __syncthreads();
     if (!cur) break;
     prev = tile;
@@ -316,9 +315,9 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   };
   // dE/dh0 = dE/da0 W0^T of tile t (wavefronts 0 and 1: row tile w), the first n_in columns stored
   auto first_layer_adjoint = [&](int64_t t) {
-    if (wave < 2) {
-      const int64_t row0 = t * RT;
-      const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+    if (wave < 2) {  // (t < 0: a buffer of no rows, nothing stored)
+      const int64_t row0 = t < 0 ? 0 : t * RT;
+      const int nvalid = t < 0 ? 0 : (int)(nrows - row0 < RT ? nrows - row0 : RT);
       floatx4 acc[1];
       mma_reg<KIND, N0 / 32, 1, H>(G0 + wave * 16 * L1, L1, RT * L1, b0w, lane, acc);
       const __amdgpu_buffer_rsrc_t R = buffer_rsrc(a.gh0 + row0 * a.ldgh, nvalid * a.ldgh * 4);
@@ -342,9 +341,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int64_t next = tile + G;
     const int64_t row0 = tile * RT;
     const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
-    if (cur) {
+    {
       // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2) in the
-      // per-layer kernels' order
+      // per-layer kernels' order (past the last tile: stale inputs, no valid
+      // rows, nothing stored)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int r = wave + 8 * q;
@@ -359,7 +359,7 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
       }
       load_g(clampt(next));
     }
-    if (prev >= 0) first_layer_adjoint(prev);
+    first_layer_adjoint(prev);
     __syncthreads();
     if (!cur) break;
     // a1 again (registers), then dE/ds1 = dE/da2 W2^T (column tile w, both
@@ -378,10 +378,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
                           r < nvalid ? gradsilu_scale(acc[i][q], x, sigmoidf_(x), 1.f) : 0.f);
         }
     }
-    if (next < ntiles) {
-      if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
-      hv = load_h0(a, clampt(next + G), nrows, tid & 255);
-    }
+    if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, next * RT + tid / (K0 / 4) < nrows, tid);
+    hv = load_h0(a, clampt(next + G), nrows, tid & 255);
     __syncthreads();
     // dE/ds0 = dE/da1 W1^T (column tile w % 4, row tile w / 4), then
     // dE/da0 = dE/ds0 SiLU'(a0) into G0; a0 of the next tile
