@@ -5,7 +5,7 @@
 // 32 -> 64 -> 128 -> 256 with SiLU after each.
 //
 // Forward: only the last pre-activation a2 leaves the kernel (x0 = u SiLU(a2)
-// is formed by its readers); a0 and a1 stay in LDS. Adjoint: a0 and a1 are
+// is formed by its readers); s0 = SiLU(a0) and s1 stay in LDS. Adjoint: a0 and a1 are
 // recomputed from h0 in the same way, then dE/da2 = g u SiLU'(a2) (with the
 // row sums dE/du += sum g SiLU(a2)) is taken back through the three layers to
 // dE/dh0; dE/da1 and dE/da0 stay in LDS. Against one launch per layer this
@@ -44,7 +44,7 @@ struct Args {
   const bf16* w0;   // forward B operands [N][K], BF16 hi then lo
   const bf16* w1;
   const bf16* w2;
-  const bf16* b0;   // adjoint B operands [K][N] (W itself), BF16 hi then lo
+  const bf16* b0;   // adjoint B operands: W as [fan-in][fan-out], BF16 hi then lo
   const bf16* b1;
   const bf16* b2;
   float* a2;        // [E][256] forward output (pre-activation)
@@ -55,9 +55,9 @@ struct Args {
   int ldgh, n_in;
 };
 
-// Row tiles r0 and r0 + 16 of A (hi rows of stride la, lo rows alo further)
-// times one 16-column fragment set of B (rows n0 .., stride lb, lo blo
-// further), K = 32 S, in K order with the BF16X3 product order per step.
+// NR consecutive 16-row tiles of A (hi rows of stride la, lo rows alo
+// further) times one 16-column fragment set of B (rows n0 .., stride lb, lo
+// blo further), K = 32 S, in K order with the BF16X3 product order per step.
 template <int KIND, int S, int NR>
 __device__ inline void mma_lds(const bf16* A, int la, int alo, const bf16* B, int lb, int blo, int n0, int lane,
                                floatx4 (&acc)[NR]) {
