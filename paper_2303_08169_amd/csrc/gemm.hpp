@@ -682,10 +682,10 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
 
   const int64_t G = gridDim.x;
   auto clampt = [&](int64_t tl) { return tl < ntiles ? tl : ntiles - 1; };
-  // One row tile: products from LDS buffer it & 1, epilogue, then the next
-  // tile's staged values into the other buffer (last read before the previous
-  // barrier) and the tile PF steps ahead into the same staging registers.
-  // Returns false after the last tile.
+  // One row tile: the next tile's staged values into the other buffer and
+  // the tile PF steps ahead into the same staging registers, then the
+  // products from LDS buffer it & 1 and the epilogue. Returns false after
+  // the last tile.
   auto one = [&](int it, int64_t tile, Stage& S) -> bool {
     // The lane-dependent offsets below are loop-invariant; recomputing them
     // from an opaque copy of the thread index each iteration is cheaper than
@@ -693,6 +693,14 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     int t = tid;
     asm volatile("" : "+v"(t));
     const int ln = t % 64;
+    // the next tile's staged values into the other buffers first (last read
+    // before the previous barrier; past the last tile they are never read)
+    // and the loads PF tiles ahead into the staging registers, so that this
+    // element work interleaves with the products below; the loads keep the
+    // same distance as when issued after the epilogue
+    const int64_t next = tile + G;
+    store(next, (it + 1) & 1, t, S);
+    fetch(clampt(tile + (PF + 1) * G), t, S);
     const bf16* a_ = As[it & 1] + (ln % 16) * LDH + (ln / 16) * 8;
     floatx4 acc[NTW];
 #pragma unroll
@@ -840,11 +848,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
         }
       }
     }
-    const int64_t next = tile + G;
-    if (next >= ntiles) return false;
-    store(next, (it + 1) & 1, t, S);
-    fetch(clampt(tile + (PF + 1) * G), t, S);
-    return true;
+    return next < ntiles;
   };
 
   int64_t tile = blockIdx.x;
