@@ -341,6 +341,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     const int64_t next = tile + G;
     const int64_t row0 = tile * RT;
     const int nvalid = (int)(nrows - row0 < RT ? nrows - row0 : RT);
+    // a1 again (registers; S0 was written before the last barrier), beside
+    // the element work of dE/da2
+    floatx4 a1[2];
+    layer1<KIND>(S0, W1s, nullptr, wave, lane, a1);
     {
       // dE/da2 = g u SiLU'(a2) into G2, and dE/du += sum g SiLU(a2) in the
       // per-layer kernels' order (past the last tile: stale inputs, no valid
@@ -362,11 +366,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
     first_layer_adjoint(prev);
     __syncthreads();
     if (!cur) break;
-    // a1 again (registers), then dE/ds1 = dE/da2 W2^T (column tile w, both
-    // row tiles) and dE/da1 = dE/ds1 SiLU'(a1) into G1
+    // dE/ds1 = dE/da2 W2^T (column tile w, both row tiles) and
+    // dE/da1 = dE/ds1 SiLU'(a1) into G1
     {
-      floatx4 a1[2], acc[2];
-      layer1<KIND>(S0, W1s, nullptr, wave, lane, a1);
+      floatx4 acc[2];
       mma_reg<KIND, N2 / 32, 2, H>(G2, LG, RT * LG, bw, lane, acc);
 #pragma unroll
       for (int i = 0; i < 2; ++i)
