@@ -6,8 +6,9 @@ The fused kernels form the same BF16 splits, the same K steps and the same
 product order as the per-layer kernels, recompute the first two layers'
 pre-activations from the same inputs in the adjoint, and add the dE/du row
 sums in the same order, so energies, per-atom energies and forces must be
-bitwise equal. Cases: 1,024 and 27,648 atoms (edge counts that leave a ragged
-last 16-row tile), both BF16 kinds, a system without edges, and an
+bitwise equal. Cases: 1,024 and 27,648 atoms (the latter leaves a ragged last
+32-row tile), both BF16 kinds, a dilute system with fewer tiles than
+workgroups (one-tile workgroups and idle ones), a system without edges, and an
 evaluation split into centre chunks."""
 import ctypes as C
 import json
@@ -66,7 +67,7 @@ def test_fused_two_body_is_bitwise_the_per_layer_path(name, prec):
     # a second call reuses dE/du and the activations' buffers: same bits again
     Ea2, Fa2, _ = _eval(auto, P, Z, L)
     auto.close()
-    print(f"{ne} edges, last tile {ne % 16} rows", flush=True)
+    print(f"{ne} edges, last 32-row tile {ne % 32 or 32} rows", flush=True)
     assert Ea == El and np.array_equal(Fa, Fl) and np.array_equal(Eia, Eil)
     assert Ea2 == Ea and np.array_equal(Fa2, Fa)
 
@@ -111,3 +112,29 @@ def test_no_edges_and_chunks():
         out[path] = _eval(p, P, Z, L)
         p.close()
     assert out["auto"][0] == out["layered"][0] and np.array_equal(out["auto"][1], out["layered"][1])
+
+
+def test_few_tiles():
+    """200 atoms in a 30 A box: about 40 edge tiles, fewer than the persistent
+    workgroups, so most workgroups have no tile and the others exactly one."""
+    cf, _, _, _, w = system("nh3_1024_l2")
+    rng = np.random.default_rng(5)
+    pos = []
+    while len(pos) < 200:  # no pair closer than 1.5 A
+        p = rng.uniform(0.0, 30.0, 3)
+        if all(np.linalg.norm((p - q + 15.0) % 30.0 - 15.0) > 1.5 for q in pos):
+            pos.append(p)
+    pos = np.array(pos)
+    z = rng.integers(0, 3, len(pos)).astype(np.int32)
+    P = torch.tensor(pos, device="cuda")
+    Z = torch.tensor(z, device="cuda")
+    res = {}
+    for path in ("layered", "auto"):
+        p = _pot(cf, w, "bf16x3", path)
+        res[path] = _eval(p, P, Z, 30.0)
+        ne, _ = p.stats()
+        p.close()
+    print(f"{ne} edges, {(ne + 31) // 32} tiles", flush=True)
+    assert 0 < ne < 32 * 256
+    assert res["auto"][0] == res["layered"][0]
+    assert np.array_equal(res["auto"][1], res["layered"][1]) and np.array_equal(res["auto"][2], res["layered"][2])
