@@ -232,8 +232,8 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   if (tid < RT * K0 / 4) put_h0<KIND>(A0, hv, tile * RT + tid / (K0 / 4) < nrows, tid);
   hv = load_h0(a, clampt(tile + G), nrows, tid & 255);
   __syncthreads();
-  // a2 = s1 W2 of tile t, column half j (from S1 buffer b), stored; t < 0
-  // stores nothing (a buffer of no rows)
+  // a2 = s1 W2 of tile t, column half j (s1: that tile's S1 buffer), stored;
+  // t < 0 stores nothing (a buffer of no rows)
   auto last_layer = [&](int64_t t, int j, const bf16* s1) {
     const int64_t row0 = t < 0 ? 0 : t * RT;
     const int nvalid = t < 0 ? 0 : (int)(nrows - row0 < RT ? nrows - row0 : RT);
@@ -269,10 +269,10 @@ __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) voi
   }
 }
 
-// Adjoint, per tile i: phase 1 = dE/da2 and dE/du of tile i and dE/dh0 of
-// tile i - 1 (wavefronts 0 and 1); phase 2 = a1 of tile i recomputed
-// (registers) and dE/ds1 -> dE/da1 into G1, the input rows of tile i + 1
-// into A0; phase 3 = dE/ds0 -> dE/da0 of tile i into G0 and a0 of tile i + 1
+// Adjoint, per tile i: phase 1 = a1 of tile i recomputed (registers), dE/da2
+// and dE/du of tile i, and dE/dh0 of tile i - 1 (wavefronts 0 and 1); phase 2
+// = dE/ds1 -> dE/da1 of tile i into G1 and the input rows of tile i + 1 into
+// A0; phase 3 = dE/ds0 -> dE/da0 of tile i into G0 and a0 of tile i + 1
 // recomputed (registers, s0 into S0). A last phase 1 ends tile i - 1 alone.
 template <int KIND>
 __global__ __launch_bounds__(NTH) __attribute__((amdgpu_waves_per_eu(2, 2))) void k_tb_bwd(Args a) {
